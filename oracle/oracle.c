@@ -1,0 +1,318 @@
+/*
+ * oracle.c -- plain, single-threaded FP64 CPU reference for the sparse COO MTTKRP / CP-ALS path
+ * of Phipps & Kolda, "Software for Sparse Tensor Decomposition on Emerging Computing
+ * Architectures" (arXiv 1809.09175).
+ *
+ * TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.  Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load or call it.  It shares no code with the HIP library.
+ *
+ * Every routine is the plain definition written out, with no blocking, fusion or reordering:
+ *   - MTTKRP: eq. (mttkrp), Section 3.  The per-term multiply order follows the paper's
+ *     description of the kernel (Section 4.1): start from x_i * lambda_j, then multiply by each
+ *     other mode's factor entry in increasing mode order.
+ *   - permutation: Section 5 sorts the entries by their mode-n coordinate with a stable sort;
+ *     here a counting sort (stable by construction).
+ *   - CP model and fit: eq. (CP), Section 3.
+ *   - CP-ALS: Section 3 defers the algorithm to Kolda & Bader; this is the textbook update.
+ *   - GCP Poisson loss: named as future work in Section 7 (generalized CP of Hong, Kolda and
+ *     Duersch); loss exp(m) - x m, derivative exp(m) - x.
+ * Parity status of every function is listed in the module's Python wrapper header.
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int check_tensor(int d, const int64_t *dims, int64_t P, const int32_t *subs)
+{
+    if (d < 1 || dims == NULL || P < 0 || (P > 0 && subs == NULL)) return ORACLE_EINVAL;
+    for (int m = 0; m < d; ++m)
+        if (dims[m] < 1) return ORACLE_EINVAL;
+    for (int64_t i = 0; i < P; ++i)
+        for (int m = 0; m < d; ++m) {
+            int32_t l = subs[i * d + m];
+            if (l < 0 || (int64_t)l >= dims[m]) return ORACLE_ERANGE;
+        }
+    return ORACLE_OK;
+}
+
+int oracle_mttkrp(int d, const int64_t *dims, int64_t P, const int32_t *subs, const double *vals,
+                  int n, int R, const double *const *A, const double *lambda, double *V)
+{
+    int rc = check_tensor(d, dims, P, subs);
+    if (rc) return rc;
+    if (n < 0 || n >= d || R < 1 || V == NULL || A == NULL || (P > 0 && vals == NULL))
+        return ORACLE_EINVAL;
+    memset(V, 0, sizeof(double) * (size_t)dims[n] * (size_t)R);
+    for (int64_t i = 0; i < P; ++i) {
+        const int32_t *l = subs + i * d;
+        double *vrow = V + (int64_t)l[n] * R;
+        for (int j = 0; j < R; ++j) {
+            double t = vals[i] * (lambda ? lambda[j] : 1.0);
+            for (int m = 0; m < d; ++m)
+                if (m != n) t *= A[m][(int64_t)l[m] * R + j];
+            vrow[j] += t;
+        }
+    }
+    return ORACLE_OK;
+}
+
+int oracle_perm(int d, const int64_t *dims, int64_t P, const int32_t *subs, int n,
+                int32_t *perm, int32_t *skey)
+{
+    int rc = check_tensor(d, dims, P, subs);
+    if (rc) return rc;
+    if (n < 0 || n >= d || P > INT32_MAX) return ORACLE_EINVAL;
+    int64_t I = dims[n];
+    int64_t *start = (int64_t *)calloc((size_t)I + 1, sizeof(int64_t));
+    if (!start) return ORACLE_EINVAL;
+    /* count entries per key, then the first output slot of each key */
+    for (int64_t i = 0; i < P; ++i) start[subs[i * d + n] + 1] += 1;
+    for (int64_t k = 0; k < I; ++k) start[k + 1] += start[k];
+    /* place entries in storage order: equal keys keep their relative order */
+    for (int64_t i = 0; i < P; ++i) {
+        int32_t k = subs[i * d + n];
+        int64_t q = start[k]++;
+        if (perm) perm[q] = (int32_t)i;
+        if (skey) skey[q] = k;
+    }
+    free(start);
+    return ORACLE_OK;
+}
+
+int oracle_model_values(int d, const int64_t *dims, int64_t P, const int32_t *subs, int R,
+                        const double *const *A, const double *lambda, double *m)
+{
+    int rc = check_tensor(d, dims, P, subs);
+    if (rc) return rc;
+    if (R < 1 || A == NULL || (P > 0 && m == NULL)) return ORACLE_EINVAL;
+    for (int64_t i = 0; i < P; ++i) {
+        const int32_t *l = subs + i * d;
+        double s = 0.0;
+        for (int j = 0; j < R; ++j) {
+            double t = lambda ? lambda[j] : 1.0;
+            for (int q = 0; q < d; ++q) t *= A[q][(int64_t)l[q] * R + j];
+            s += t;
+        }
+        m[i] = s;
+    }
+    return ORACLE_OK;
+}
+
+int oracle_gram(int64_t I, int R, const double *A, double *G)
+{
+    if (I < 0 || R < 1 || (I > 0 && A == NULL) || G == NULL) return ORACLE_EINVAL;
+    for (int a = 0; a < R; ++a)
+        for (int b = 0; b < R; ++b) {
+            double s = 0.0;
+            for (int64_t k = 0; k < I; ++k) s += A[k * R + a] * A[k * R + b];
+            G[a * R + b] = s;
+        }
+    return ORACLE_OK;
+}
+
+/* Lower Cholesky factor of the symmetric matrix S (R x R): S = L L^T.  A pivot that is not
+ * larger than R * DBL_EPSILON * max_k S(k,k) makes the matrix singular for this purpose. */
+static int cholesky_lower(int R, const double *S, double *L)
+{
+    double maxdiag = 0.0;
+    for (int k = 0; k < R; ++k)
+        if (S[k * R + k] > maxdiag) maxdiag = S[k * R + k];
+    double tol = (double)R * DBL_EPSILON * maxdiag;
+    memset(L, 0, sizeof(double) * (size_t)R * (size_t)R);
+    for (int c = 0; c < R; ++c) {
+        double piv = S[c * R + c];
+        for (int k = 0; k < c; ++k) piv -= L[c * R + k] * L[c * R + k];
+        if (!(piv > tol)) return ORACLE_ESINGULAR;
+        double lcc = sqrt(piv);
+        L[c * R + c] = lcc;
+        for (int r = c + 1; r < R; ++r) {
+            double s = S[r * R + c];
+            for (int k = 0; k < c; ++k) s -= L[r * R + k] * L[c * R + k];
+            L[r * R + c] = s / lcc;
+        }
+    }
+    return ORACLE_OK;
+}
+
+int oracle_cp_als_mode(int d, const int64_t *dims, int64_t P, const int32_t *subs,
+                       const double *vals, int n, int R, double *const *A, double *lambda,
+                       double *G)
+{
+    if (n < 0 || n >= d || R < 1 || A == NULL || lambda == NULL || G == NULL)
+        return ORACLE_EINVAL;
+    int64_t I = dims[n];
+    double *V = (double *)malloc(sizeof(double) * (size_t)I * (size_t)R);
+    double *Gam = (double *)malloc(sizeof(double) * (size_t)R * (size_t)R);
+    double *L = (double *)malloc(sizeof(double) * (size_t)R * (size_t)R);
+    double *y = (double *)malloc(sizeof(double) * (size_t)R);
+    int rc = ORACLE_EINVAL;
+    if (!V || !Gam || !L || !y) goto done;
+
+    rc = oracle_mttkrp(d, dims, P, subs, vals, n, R, (const double *const *)A, NULL, V);
+    if (rc) goto done;
+
+    for (int a = 0; a < R * R; ++a) Gam[a] = 1.0;
+    for (int m = 0; m < d; ++m)
+        if (m != n)
+            for (int a = 0; a < R * R; ++a) Gam[a] *= G[(size_t)m * R * R + a];
+
+    rc = cholesky_lower(R, Gam, L);
+    if (rc) goto done;
+
+    /* row k of the new factor solves a Gamma = v, i.e. Gamma a^T = v^T (Gamma symmetric):
+     * L y = v (forward), then L^T a = y (backward). */
+    for (int64_t k = 0; k < I; ++k) {
+        const double *v = V + k * R;
+        double *a = A[n] + k * R;
+        for (int c = 0; c < R; ++c) {
+            double s = v[c];
+            for (int q = 0; q < c; ++q) s -= L[c * R + q] * y[q];
+            y[c] = s / L[c * R + c];
+        }
+        for (int c = R - 1; c >= 0; --c) {
+            double s = y[c];
+            for (int q = c + 1; q < R; ++q) s -= L[q * R + c] * a[q];
+            a[c] = s / L[c * R + c];
+        }
+    }
+
+    for (int j = 0; j < R; ++j) {
+        double s = 0.0;
+        for (int64_t k = 0; k < I; ++k) s += A[n][k * R + j] * A[n][k * R + j];
+        lambda[j] = sqrt(s);
+    }
+    for (int64_t k = 0; k < I; ++k)
+        for (int j = 0; j < R; ++j)
+            if (lambda[j] > 0.0) A[n][k * R + j] /= lambda[j];
+
+    rc = oracle_gram(I, R, A[n], G + (size_t)n * R * R);
+done:
+    free(V);
+    free(Gam);
+    free(L);
+    free(y);
+    return rc;
+}
+
+int oracle_cp_als_sweep(int d, const int64_t *dims, int64_t P, const int32_t *subs,
+                        const double *vals, int R, double *const *A, double *lambda, double *G)
+{
+    for (int n = 0; n < d; ++n) {
+        int rc = oracle_cp_als_mode(d, dims, P, subs, vals, n, R, A, lambda, G);
+        if (rc) return rc;
+    }
+    return ORACLE_OK;
+}
+
+int oracle_fit(int d, const int64_t *dims, int64_t P, const int32_t *subs, const double *vals,
+               int R, const double *const *A, const double *lambda, double *fit, double *parts)
+{
+    int rc = check_tensor(d, dims, P, subs);
+    if (rc) return rc;
+    if (R < 1 || A == NULL || fit == NULL || (P > 0 && vals == NULL)) return ORACLE_EINVAL;
+    double *m = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    double *Gall = (double *)malloc(sizeof(double) * (size_t)R * (size_t)R);
+    double *Gm = (double *)malloc(sizeof(double) * (size_t)R * (size_t)R);
+    rc = ORACLE_EINVAL;
+    if (!m || !Gall || !Gm) goto done;
+    rc = oracle_model_values(d, dims, P, subs, R, A, lambda, m);
+    if (rc) goto done;
+
+    double xx = 0.0, xm = 0.0, mm = 0.0;
+    for (int64_t i = 0; i < P; ++i) {
+        xx += vals[i] * vals[i];
+        xm += vals[i] * m[i];
+    }
+    for (int a = 0; a < R * R; ++a) Gall[a] = 1.0;
+    for (int q = 0; q < d; ++q) {
+        oracle_gram(dims[q], R, A[q], Gm);
+        for (int a = 0; a < R * R; ++a) Gall[a] *= Gm[a];
+    }
+    for (int a = 0; a < R; ++a)
+        for (int b = 0; b < R; ++b) {
+            double la = lambda ? lambda[a] : 1.0, lb = lambda ? lambda[b] : 1.0;
+            mm += la * Gall[a * R + b] * lb;
+        }
+    double r2 = xx - 2.0 * xm + mm;
+    if (r2 < 0.0) r2 = 0.0;
+    *fit = 1.0 - sqrt(r2) / sqrt(xx);
+    if (parts) {
+        parts[0] = xx;
+        parts[1] = xm;
+        parts[2] = mm;
+    }
+done:
+    free(m);
+    free(Gall);
+    free(Gm);
+    return rc;
+}
+
+int oracle_gcp_poisson(int d, const int64_t *dims, int64_t P, const int32_t *subs,
+                       const double *vals, const double *w, int R, const double *const *A,
+                       double *loss, double *const *grads)
+{
+    int rc = check_tensor(d, dims, P, subs);
+    if (rc) return rc;
+    if (R < 1 || A == NULL || loss == NULL || (P > 0 && vals == NULL)) return ORACLE_EINVAL;
+    double *m = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    double *y = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    rc = ORACLE_EINVAL;
+    if (!m || !y) goto done;
+    rc = oracle_model_values(d, dims, P, subs, R, A, NULL, m);
+    if (rc) goto done;
+    double L = 0.0;
+    for (int64_t i = 0; i < P; ++i) {
+        double wi = w ? w[i] : 1.0;
+        L += wi * (exp(m[i]) - vals[i] * m[i]);
+        y[i] = wi * (exp(m[i]) - vals[i]);
+    }
+    *loss = L;
+    if (grads)
+        for (int n = 0; n < d && rc == ORACLE_OK; ++n)
+            rc = oracle_mttkrp(d, dims, P, subs, y, n, R, A, NULL, grads[n]);
+done:
+    free(m);
+    free(y);
+    return rc;
+}
+
+static double bits_to_float_as_double(uint32_t b)
+{
+    float f;
+    memcpy(&f, &b, sizeof f);
+    return (double)f;
+}
+
+uint16_t oracle_bf16_rne(uint32_t x)
+{
+    uint32_t sign = x & 0x80000000u;
+    uint32_t mag = x & 0x7fffffffu;
+    if (mag > 0x7f800000u) /* NaN: keep sign and top payload, force the quiet bit */
+        return (uint16_t)((x >> 16) | 0x0040u);
+    if (mag == 0x7f800000u) return (uint16_t)(x >> 16); /* +-inf */
+    /* the BF16 magnitudes just below (truncation) and just above the input */
+    uint32_t lo_bits = mag & 0xffff0000u;
+    if (lo_bits == mag) return (uint16_t)((sign | mag) >> 16); /* exactly representable */
+    uint32_t hi_bits = lo_bits + 0x00010000u;
+    double v = bits_to_float_as_double(mag);
+    double lo = bits_to_float_as_double(lo_bits);
+    /* the next BF16 above the largest finite one is 2^128, which rounds to infinity */
+    double hi = (hi_bits == 0x7f800000u) ? ldexp(1.0, 128) : bits_to_float_as_double(hi_bits);
+    double dlo = v - lo, dhi = hi - v; /* exact in double */
+    uint32_t pick;
+    if (dlo < dhi) pick = lo_bits;
+    else if (dhi < dlo) pick = hi_bits;
+    else pick = ((lo_bits >> 16) & 1u) ? hi_bits : lo_bits; /* tie: even last bit */
+    return (uint16_t)((sign | pick) >> 16);
+}
+
+int oracle_bf16_rne_array(int64_t n, const uint32_t *in, uint16_t *out)
+{
+    if (n < 0 || (n > 0 && (in == NULL || out == NULL))) return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n; ++i) out[i] = oracle_bf16_rne(in[i]);
+    return ORACLE_OK;
+}

@@ -1,0 +1,310 @@
+"""Pins for the FP64 CPU oracle: each check is an independent route to the same number
+(brute force, closed forms, textbook library routines, invariants), never the oracle's own
+formula typed again.  CPU only."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _rand_coo(rng, dims, P, dup=True, vals="normal"):
+    subs = np.stack([rng.integers(0, I, size=P) for I in dims], axis=1).astype(np.int32)
+    if dup and P >= 4:
+        subs[P // 2] = subs[0]          # force repeated coordinates
+        subs[P // 2 + 1] = subs[1]
+    v = rng.standard_normal(P) if vals == "normal" else rng.random(P)
+    return subs, v
+
+
+def _dense(subs, vals, dims):
+    X = np.zeros(dims)
+    np.add.at(X, tuple(subs[:, m] for m in range(len(dims))), vals)
+    return X
+
+
+def _unfold(X, n):
+    """Mode-n unfolding: rows = mode n, columns = remaining modes in increasing order, the
+    last one varying fastest."""
+    return np.moveaxis(X, n, 0).reshape(X.shape[n], -1)
+
+
+def _khatri_rao(mats):
+    """Column-wise Kronecker product, first matrix's index slowest (matches _unfold)."""
+    R = mats[0].shape[1]
+    cols = []
+    for j in range(R):
+        c = np.ones(1)
+        for M in mats:
+            c = np.kron(c, M[:, j])
+        cols.append(c)
+    return np.stack(cols, axis=1)
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ------------------------------------------------------------------------------------- MTTKRP
+
+@pytest.mark.parametrize("dims", [(4, 5, 6), (3, 2, 5, 4), (6, 1, 3), (2, 3, 2, 2, 3)])
+@pytest.mark.parametrize("R", [1, 3, 7])
+def test_mttkrp_brute_force(dims, R):
+    rng = np.random.default_rng(sum(dims) * 10 + R)
+    subs, vals = _rand_coo(rng, dims, 40)
+    A = [rng.standard_normal((I, R)) for I in dims]
+    lam = rng.standard_normal(R)
+    X = _dense(subs, vals, dims)
+    for n in range(len(dims)):
+        others = [A[m] for m in range(len(dims)) if m != n]
+        ref = _unfold(X, n) @ _khatri_rao(others) @ np.diag(lam)
+        got = oracle.mttkrp(subs, vals, dims, A, n, lam)
+        assert _relerr(got, ref) < 1e-13
+        got1 = oracle.mttkrp(subs, vals, dims, A, n)         # lambda omitted = ones
+        ref1 = _unfold(X, n) @ _khatri_rao(others)
+        assert _relerr(got1, ref1) < 1e-13
+
+
+def test_mttkrp_rank1_closed_form():
+    rng = np.random.default_rng(7)
+    dims = (5, 4, 3)
+    a, b, c = (rng.random(I) + 0.5 for I in dims)
+    cells = np.array(list(itertools.product(*[range(I) for I in dims])), dtype=np.int32)
+    vals = a[cells[:, 0]] * b[cells[:, 1]] * c[cells[:, 2]]
+    R = 4
+    A = [rng.standard_normal((I, R)) for I in dims]
+    lam = rng.random(R) + 0.1
+    vecs = (a, b, c)
+    for n in range(3):
+        got = oracle.mttkrp(cells, vals, dims, A, n, lam)
+        ref = np.outer(vecs[n], lam)
+        for m in range(3):
+            if m != n:
+                ref = ref * (vecs[m] @ A[m])[None, :]
+        assert _relerr(got, ref) < 1e-13
+
+
+def test_mttkrp_two_way_is_sparse_matrix_product():
+    rng = np.random.default_rng(3)
+    dims = (7, 9)
+    subs, vals = _rand_coo(rng, dims, 30)
+    A = [rng.standard_normal((I, 5)) for I in dims]
+    X = _dense(subs, vals, dims)
+    assert _relerr(oracle.mttkrp(subs, vals, dims, A, 0), X @ A[1]) < 1e-14
+    assert _relerr(oracle.mttkrp(subs, vals, dims, A, 1), X.T @ A[0]) < 1e-14
+
+
+def test_mttkrp_linear_duplicates_and_order():
+    rng = np.random.default_rng(11)
+    dims = (6, 5, 4)
+    subs, x = _rand_coo(rng, dims, 50)
+    y = rng.standard_normal(50)
+    A = [rng.standard_normal((I, 3)) for I in dims]
+    for n in range(3):
+        vx = oracle.mttkrp(subs, x, dims, A, n)
+        vy = oracle.mttkrp(subs, y, dims, A, n)
+        vxy = oracle.mttkrp(subs, 2.0 * x - 0.5 * y, dims, A, n)
+        assert _relerr(vxy, 2.0 * vx - 0.5 * vy) < 1e-13
+        split = oracle.mttkrp(np.concatenate([subs, subs]), np.concatenate([x, x]) * 0.5,
+                              dims, A, n)
+        assert _relerr(split, vx) < 1e-14
+        p = rng.permutation(50)
+        assert _relerr(oracle.mttkrp(subs[p], x[p], dims, A, n), vx) < 1e-14
+
+
+def test_mttkrp_empty_and_errors():
+    dims = (3, 4, 5)
+    A = [np.ones((I, 2)) for I in dims]
+    V = oracle.mttkrp(np.zeros((0, 3), np.int32), np.zeros(0), dims, A, 1)
+    assert V.shape == (4, 2) and not V.any()
+    with pytest.raises(oracle.OracleError):
+        oracle.mttkrp(np.array([[0, 4, 0]], np.int32), np.ones(1), dims, A, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.mttkrp(np.array([[0, -1, 0]], np.int32), np.ones(1), dims, A, 0)
+
+
+# ----------------------------------------------------------------------------------- permutation
+
+@pytest.mark.parametrize("I", [1, 3, 17, 1000])
+def test_perm_matches_stable_argsort(I):
+    rng = np.random.default_rng(I)
+    dims = (I, 5, 9)
+    subs = np.stack([rng.integers(0, D, size=5000) for D in dims], axis=1).astype(np.int32)
+    for n in range(3):
+        p, k = oracle.perm(subs, dims, n)
+        ref = np.argsort(subs[:, n], kind="stable")
+        assert np.array_equal(p, ref)
+        assert np.array_equal(k, subs[ref, n])
+        assert np.array_equal(np.sort(p), np.arange(5000))   # bijection
+        assert np.all(np.diff(k) >= 0)                        # keys non-decreasing
+        # stability: equal keys appear in storage order
+        same = np.diff(k) == 0
+        assert np.all(np.diff(p)[same] > 0)
+
+
+# ------------------------------------------------------------------------- model, fit, gram
+
+def test_model_values_and_gram_match_dense():
+    rng = np.random.default_rng(5)
+    dims = (4, 3, 5)
+    R = 3
+    A = [rng.standard_normal((I, R)) for I in dims]
+    lam = rng.random(R)
+    M = np.einsum("r,ir,jr,kr->ijk", lam, *A)
+    cells = np.array(list(itertools.product(*[range(I) for I in dims])), dtype=np.int32)
+    m = oracle.model_values(cells, dims, A, lam)
+    assert _relerr(m, M[cells[:, 0], cells[:, 1], cells[:, 2]]) < 1e-14
+    assert _relerr(oracle.gram(A[0]), A[0].T @ A[0]) < 1e-15
+
+
+def test_fit_matches_brute_force_residual():
+    rng = np.random.default_rng(9)
+    dims = (6, 5, 4)
+    cells = rng.choice(int(np.prod(dims)), size=60, replace=False)
+    subs = np.stack(np.unravel_index(cells, dims), axis=1).astype(np.int32)
+    vals = rng.random(60)
+    R = 2
+    A = [rng.random((I, R)) for I in dims]
+    lam = rng.random(R)
+    X = _dense(subs, vals, dims)
+    M = np.einsum("r,ir,jr,kr->ijk", lam, *A)
+    ref = 1.0 - np.linalg.norm(X - M) / np.linalg.norm(X)
+    f, parts = oracle.fit(subs, vals, dims, A, lam, return_parts=True)
+    assert abs(f - ref) < 1e-12
+    assert abs(parts[0] - np.sum(X * X)) < 1e-12 * parts[0]
+    assert abs(parts[1] - np.sum(X * M)) < 1e-12 * abs(parts[1])
+    assert abs(parts[2] - np.sum(M * M)) < 1e-12 * parts[2]
+
+
+# ----------------------------------------------------------------------------------- CP-ALS
+
+def _state(A):
+    lam = np.ones(A[0].shape[1])
+    G = np.stack([a.T @ a for a in A])
+    return lam, G
+
+
+def test_cp_als_mode_solves_normal_equations_and_matches_lstsq():
+    rng = np.random.default_rng(21)
+    dims = (7, 6, 5)
+    cells = rng.choice(int(np.prod(dims)), size=120, replace=False)
+    subs = np.stack(np.unravel_index(cells, dims), axis=1).astype(np.int32)
+    vals = rng.random(120)
+    R = 3
+    A = [rng.random((I, R)) for I in dims]
+    lam, G = _state(A)
+    X = _dense(subs, vals, dims)
+    for n in range(3):
+        A2, lam2, G2 = oracle.cp_als_mode(subs, vals, dims, A, lam, G, n)
+        others = [A[m] for m in range(3) if m != n]
+        KR = _khatri_rao(others)
+        # independent route: dense least squares  min || X_(n) - B KR^T ||
+        B = np.linalg.lstsq(KR, _unfold(X, n).T, rcond=None)[0].T
+        nrm = np.linalg.norm(B, axis=0)
+        assert _relerr(lam2, nrm) < 1e-10
+        assert _relerr(A2[n], B / nrm) < 1e-10
+        assert np.allclose(np.linalg.norm(A2[n], axis=0), 1.0, atol=1e-14)
+        assert _relerr(G2[n], A2[n].T @ A2[n]) < 1e-14
+        for m in range(3):                 # other modes untouched
+            if m != n:
+                assert np.array_equal(A2[m], A[m]) and np.array_equal(G2[m], G[m])
+
+
+def _dense_fit(X, A, lam):
+    M = np.einsum("r,ir,jr,kr->ijk", lam, *A)
+    return 1.0 - np.linalg.norm(X - M) / np.linalg.norm(X)
+
+
+@pytest.mark.parametrize("start", ["near", "random"])
+def test_cp_als_recovers_exact_low_rank(start):
+    rng = np.random.default_rng(31)
+    dims = (12, 10, 8)
+    R = 3
+    T = [rng.standard_normal((I, R)) for I in dims]
+    X = np.einsum("ir,jr,kr->ijk", *T)
+    cells = np.array(list(itertools.product(*[range(I) for I in dims])), dtype=np.int32)
+    vals = X[cells[:, 0], cells[:, 1], cells[:, 2]]
+    if start == "near":
+        A = [t + 1e-2 * rng.standard_normal(t.shape) for t in T]
+    else:
+        A = [rng.standard_normal(t.shape) for t in T]
+    lam, G = _state(A)
+    prev = -np.inf
+    fit = None
+    for it in range(2000):
+        A, lam, G = oracle.cp_als_sweep(cells, vals, dims, A, lam, G)
+        fit = _dense_fit(X, A, lam)
+        assert fit >= prev - 1e-12, f"fit decreased at sweep {it}: {prev} -> {fit}"
+        if fit - prev < 1e-15 and fit > 1 - 1e-10:
+            break
+        prev = fit
+    assert fit > 1.0 - 1e-10
+
+
+def test_cp_als_singular_gram_reported():
+    dims = (4, 3, 3)
+    cells = np.array(list(itertools.product(*[range(I) for I in dims])), dtype=np.int32)
+    vals = np.ones(len(cells))
+    A = [np.ones((I, 2)) for I in dims]      # two identical columns: Gamma is rank one
+    lam, G = _state(A)
+    with pytest.raises(oracle.OracleError, match="singular"):
+        oracle.cp_als_mode(cells, vals, dims, A, lam, G, 0)
+
+
+# -------------------------------------------------------------------------------------- GCP
+
+def test_gcp_poisson_loss_dense_and_gradient_finite_differences():
+    rng = np.random.default_rng(41)
+    dims = (5, 4, 3)
+    cells = rng.choice(int(np.prod(dims)), size=30, replace=False)
+    subs = np.stack(np.unravel_index(cells, dims), axis=1).astype(np.int32)
+    vals = rng.poisson(2.0, size=30).astype(np.float64)
+    w = rng.random(30) + 0.5
+    R = 2
+    A = [0.5 * rng.random((I, R)) for I in dims]
+    loss, grads = oracle.gcp_poisson(subs, vals, dims, A, w)
+    M = np.einsum("ir,jr,kr->ijk", *A)[subs[:, 0], subs[:, 1], subs[:, 2]]
+    assert abs(loss - np.sum(w * (np.exp(M) - vals * M))) < 1e-12 * abs(loss)
+    for n in range(3):
+        for (k, j) in [(0, 0), (dims[n] - 1, 1), (1, 0)]:
+            h = 1e-6 * max(1.0, abs(A[n][k, j]))
+            Ap = [a.copy() for a in A]
+            Am = [a.copy() for a in A]
+            Ap[n][k, j] += h
+            Am[n][k, j] -= h
+            fd = (oracle.gcp_poisson(subs, vals, dims, Ap, w, grads=False)
+                  - oracle.gcp_poisson(subs, vals, dims, Am, w, grads=False)) / (2 * h)
+            assert abs(fd - grads[n][k, j]) < 1e-7 * max(1.0, abs(fd))
+
+
+# ------------------------------------------------------------------------------------- BF16
+
+def _torch_bf16_bits(bits):
+    import torch
+    t = torch.from_numpy(bits.view(np.float32).copy()).to(torch.bfloat16)
+    return t.view(torch.int16).numpy().view(np.uint16)
+
+
+def test_bf16_rne_matches_torch_on_samples_and_boundaries():
+    rng = np.random.default_rng(51)
+    rnd = rng.integers(0, 1 << 32, size=1 << 21, dtype=np.uint64).astype(np.uint32)
+    hi = np.arange(0, 1 << 16, dtype=np.uint32) << 16
+    edges = np.concatenate([hi | 0x8000, hi | 0x7FFF, hi | 0x8001, hi, hi | 0xFFFF])
+    bits = np.concatenate([rnd, edges])
+    f = bits.view(np.float32)
+    finite = ~np.isnan(f)
+    got = oracle.bf16_rne(bits)
+    ref = _torch_bf16_bits(bits)
+    assert np.array_equal(got[finite], ref[finite])
+    nan_bits = bits[~finite]
+    g = got[~finite]
+    assert np.all((g & 0x7F80) == 0x7F80) and np.all(g & 0x0040)      # still NaN, quiet
+    assert np.array_equal(g >> 15, (nan_bits >> 31).astype(np.uint16))  # sign kept
+    # ties go to the even neighbour: 1 + 2^-8 sits halfway between 1 and 1 + 2^-7
+    assert oracle.bf16_rne(np.array([0x3F808000], np.uint32))[0] == 0x3F80
+    assert oracle.bf16_rne(np.array([0x3F818000], np.uint32))[0] == 0x3F82
+    # largest finite FP32 rounds to infinity; the largest finite BF16 stays
+    assert oracle.bf16_rne(np.array([0x7F7FFFFF], np.uint32))[0] == 0x7F80
+    assert oracle.bf16_rne(np.array([0x7F7F0000], np.uint32))[0] == 0x7F7F
