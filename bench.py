@@ -1,0 +1,270 @@
+"""Benchmark: all-mode MTTKRP on the 1e8-entry power-law tensor (500,000 x 500,000 x 20,000,
+Zipf(1.1) subscripts per mode, FP32 values and factors) on one MI355X.
+
+One step = one MTTKRP of every mode (zero V, then the permuted-traversal kernel), R = 32.  The
+metric is effective GB/s under the paper's bandwidth model (bytes per entry = value + d
+subscripts + (d-1) gathered factor rows + one output row), the same byte count for both
+kernels so effective GB/s is proportional to 1/time.  Also reported: the atomic kernel, R = 16
+and 64, the permutation-build cost against one CP-ALS sweep, a STREAM-style triad, the BF16
+factor speedup on the 4-way skewed tensor, the dominant kernel's roofline fraction, and the
+FP64 CPU oracle timed on a bounded sample of the same tensor.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def model_bytes(d, R, s_val=4, s_idx=4, s_f=4, s_out=4):
+    """Bytes per entry of the paper's MTTKRP bandwidth model (Sec. 6.1), typed per operand."""
+    return s_val + d * s_idx + (d - 1) * R * s_f + R * s_out
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("mttkrp_kernels.h", "mttkrp.hip", "mttkrp_f32.hip", "spt_internal.h"):
+        with open(os.path.join(ROOT, "paper_1809_09175_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_counters():
+    """HBM traffic per dispatch of the dominant kernel, from the committed rocprofv3 counter
+    summary; None when absent or taken from a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "mttkrp_perm_powerlaw3_R32_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--rank", type=int, default=32)
+    ap.add_argument("--quick", action="store_true", help="skip the extra workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, ROOT)
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import datagen
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.time()
+    X = datagen.powerlaw3()
+    log(f"generated powerlaw3 ({X.nnz} entries) in {time.time() - t0:.1f}s")
+    subs = torch.from_numpy(X.subs).to(dev)
+    vals = torch.from_numpy(X.vals).to(dev)
+    T = spt.SparseTensor(subs, vals, X.dims)
+    T.validate()
+    del subs, vals
+
+    def timed(fn, reps=1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # permutation build (excluded from MTTKRP time, reported against a CP-ALS sweep)
+    T.permute()
+    torch.cuda.synchronize()
+    sort_ms = timed(lambda: T.permute())
+    log(f"permutation build, all modes: {sort_ms:.2f} ms")
+
+    d = X.d
+    P = X.nnz
+
+    def factors_for(R, dtype=np.float32):
+        return [torch.from_numpy(a).to(dev) for a in datagen.factors(X.dims, R, seed=7, dtype=dtype)]
+
+    def run_modes(R, algo, A, outs, events=None):
+        for n in range(d):
+            if events is not None:
+                events[n][0].record(stream)
+            spt.mttkrp(T, A, n, algo=algo, out=outs[n])
+            if events is not None:
+                events[n][1].record(stream)
+
+    def measure(R, algo, steps, warmup, A=None):
+        A = A if A is not None else factors_for(R)
+        outs = [torch.empty((I, R), dtype=torch.float32, device=dev) for I in X.dims]
+        for _ in range(warmup):
+            run_modes(R, algo, A, outs)
+        torch.cuda.synchronize()
+        per_mode = np.zeros(d)
+        ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+               for _ in range(d)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(stream)
+        for k in range(steps):
+            run_modes(R, algo, A, outs, ev[k])
+        g1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        total_ms = g0.elapsed_time(g1)
+        for k in range(steps):
+            for n in range(d):
+                per_mode[n] += ev[k][n][0].elapsed_time(ev[k][n][1])
+        per_mode /= steps
+        ms_step = total_ms / steps
+        gbs = P * model_bytes(d, R) * d / (ms_step * 1e-3) / 1e9
+        return {"ms_per_step": ms_step, "gbs": gbs, "per_mode_ms": per_mode.tolist(),
+                "wall_s": wall}
+
+    R = args.rank
+    main_res = measure(R, "permuted", args.steps, args.warmup)
+    log(f"R={R} permuted: {main_res['ms_per_step']:.3f} ms/step, {main_res['gbs']:.0f} GB/s")
+    atomic_res = measure(R, "atomic", max(3, args.steps // 2), 2)
+    log(f"R={R} atomic:   {atomic_res['ms_per_step']:.3f} ms/step, {atomic_res['gbs']:.0f} GB/s")
+
+    extras = {}
+    per_rank = {}
+    if not args.quick:
+        for r in (16, 32, 64):
+            if r == R:
+                per_rank[str(r)] = {"permuted_gbs": round(main_res["gbs"], 1),
+                                    "atomic_gbs": round(atomic_res["gbs"], 1),
+                                    "permuted_ms": round(main_res["ms_per_step"], 3),
+                                    "atomic_ms": round(atomic_res["ms_per_step"], 3)}
+                continue
+            p = measure(r, "permuted", 5, 1)
+            a = measure(r, "atomic", 3, 1)
+            per_rank[str(r)] = {"permuted_gbs": round(p["gbs"], 1), "atomic_gbs": round(a["gbs"], 1),
+                                "permuted_ms": round(p["ms_per_step"], 3),
+                                "atomic_ms": round(a["ms_per_step"], 3)}
+            log(f"R={r}: permuted {p['gbs']:.0f} GB/s, atomic {a['gbs']:.0f} GB/s")
+        # BF16 factors on the same tensor
+        A32 = factors_for(R)
+        A16 = [spt.to_bf16(a) for a in A32]
+        b16 = measure(R, "permuted", 5, 1, A=A16)
+        extras["bf16_factors_same_tensor"] = {
+            "ms_per_step": round(b16["ms_per_step"], 3),
+            "speedup_vs_fp32": round(main_res["ms_per_step"] / b16["ms_per_step"], 3)}
+        log(f"BF16 factors: {b16['ms_per_step']:.3f} ms/step")
+        # one CP-ALS sweep (FP32 factors, permuted MTTKRP) and the fit
+        st = spt.CPState(T, factors_for(R))
+        st.sweep()
+        torch.cuda.synchronize()
+        sweep_ms = timed(lambda: st.sweep(), reps=3)
+        t_fit = time.perf_counter()
+        st.fit()
+        fit_ms = (time.perf_counter() - t_fit) * 1e3
+        extras["cp_als_sweep_ms"] = round(sweep_ms, 3)
+        extras["cp_fit_ms"] = round(fit_ms, 3)
+        extras["sort_ms_all_modes"] = round(sort_ms, 3)
+        extras["sort_over_cp_als_iteration"] = round(sort_ms / (sweep_ms + fit_ms), 3)
+        log(f"CP-ALS sweep {sweep_ms:.2f} ms, fit {fit_ms:.2f} ms")
+        del st
+        # STREAM-style triad on 3 x 1 GiB
+        n = 1 << 28
+        a = torch.empty(n, dtype=torch.float32, device=dev)
+        b = torch.rand(n, dtype=torch.float32, device=dev)
+        c = torch.rand(n, dtype=torch.float32, device=dev)
+        spt.stream_triad(a, b, c)
+        tri_ms = timed(lambda: spt.stream_triad(a, b, c), reps=10)
+        triad_gbs = 3 * 4 * n / (tri_ms * 1e-3) / 1e9
+        extras["stream_triad_gbs"] = round(triad_gbs, 1)
+        extras["pct_of_measured_stream"] = round(100.0 * main_res["gbs"] / triad_gbs, 1)
+        del a, b, c
+        log(f"triad {triad_gbs:.0f} GB/s")
+
+    # roofline of the dominant kernel (the permuted MTTKRP); per launch = one mode
+    avg_launch_ms = float(np.mean(main_res["per_mode_ms"]))
+    per_launch_bytes = P * model_bytes(d, R)
+    achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
+    traffic = read_counters()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_mttkrp_perm<3,32,1,float>",
+                "per_launch_model_bytes": per_launch_bytes,
+                "avg_launch_ms": round(avg_launch_ms, 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        S = 20_000_000
+        A = [a.astype(np.float64) for a in datagen.factors(X.dims, R, seed=7, dtype=np.float32)]
+        sub_s, sub_v = X.subs[:S], X.vals[:S]
+        t = time.perf_counter()
+        for n in range(d):
+            oracle.mttkrp(sub_s, sub_v, X.dims, A, n)
+        cpu_s = time.perf_counter() - t
+        cpu = {"value": round(S * model_bytes(d, R) * d / cpu_s / 1e9, 3), "unit": "GB/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"first {S} of {P} entries of the same tensor, all {d} modes, R={R}, "
+                         f"FP64 single-threaded ({cpu_s:.1f} s)"}
+        log(f"CPU oracle: {cpu['value']} GB/s effective on the sample")
+
+    out = {
+        "metric": "MTTKRP effective HBM GB/s (% of peak), permuted vs atomic; BF16/batched vs FP32 speedup",
+        "value": round(main_res["gbs"], 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "powerlaw3: 3-way 500000x500000x20000, 1e8 entries, Zipf(1.1) "
+                               "per mode, FP32 values and factors, all-mode MTTKRP",
+                   "rank": R, "algo": "permuted", "nnz": P},
+        "pct_of_hbm_peak": round(100.0 * main_res["gbs"] / HBM_PEAK_GBS, 1),
+        "gflops": round(P * d * (d + 1) * R / (main_res["ms_per_step"] * 1e-3) / 1e9, 1),
+        "atomic": {"gbs": round(atomic_res["gbs"], 1), "ms_per_step": round(atomic_res["ms_per_step"], 4),
+                   "permuted_speedup": round(atomic_res["ms_per_step"] / main_res["ms_per_step"], 3)},
+        "per_mode_ms": [round(x, 4) for x in main_res["per_mode_ms"]],
+        "per_rank": per_rank,
+        "extras": extras,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

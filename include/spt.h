@@ -1,0 +1,218 @@
+/*
+ * spt.h -- C ABI of libspt, the MI355X (gfx950) sparse COO tensor library: per-mode
+ * permutations, MTTKRP (atomic and permuted traversal), CP-ALS update, fit and the
+ * generalized-CP Poisson loss.
+ *
+ * Method: Phipps & Kolda, "Software for Sparse Tensor Decomposition on Emerging Computing
+ * Architectures", arXiv 1809.09175.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Pointers documented "device" point to GPU memory owned by the caller (for example torch
+ *    tensors).  The library never allocates device memory: every buffer it needs is carved from
+ *    a caller-provided workspace whose size the matching *_workspace_bytes() call returns.  The
+ *    caller keeps every borrowed buffer alive (and unmodified where stated) while a handle that
+ *    refers to it exists.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls only enqueue
+ *    work on it and return at once, unless documented as synchronising.
+ *  - Indices are 0-based.  Subscripts and permutations are int32 (so at most 2^31-1 entries and
+ *    mode lengths); sizes and entry counts are int64 in the interface.
+ *  - Dense matrices (factors A^(m), MTTKRP results V, Gram matrices) are row-major.
+ *  - Every call returns an spt_status.  Argument errors are found on the host before anything
+ *    is enqueued and leave all outputs untouched.  Errors found on the GPU (a subscript out of
+ *    range, a singular Gram matrix) set a status word inside the tensor's workspace; they are
+ *    returned by the next synchronising call on that tensor (spt_tensor_validate, spt_cp_fit,
+ *    spt_tensor_status).
+ *  - Thread safety: a tensor handle may be used concurrently by several host threads for
+ *    read-only calls (MTTKRP, fit, model values) once its permutations exist; calls that write
+ *    into the workspace (create, permute, cp_* steps) must not overlap on one tensor.
+ */
+#ifndef SPT_H
+#define SPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spt_status {
+    SPT_OK = 0,
+    SPT_EINVAL = -1,       /* invalid argument (null pointer, bad mode, bad size, ...) */
+    SPT_ERANGE = -2,       /* a subscript is outside [0, I_m) */
+    SPT_EHIP = -3,         /* a HIP runtime call failed */
+    SPT_ESINGULAR = -4,    /* a Gram matrix product was not positive definite */
+    SPT_EWORKSPACE = -5,   /* workspace too small or misaligned (256-byte alignment) */
+    SPT_EUNSUPPORTED = -6, /* valid but unsupported combination (order, rank, dtype) */
+    SPT_ESTATE = -7        /* call out of order (e.g. permuted MTTKRP before permute) */
+} spt_status;
+
+typedef enum spt_dtype { SPT_F64 = 0, SPT_F32 = 1, SPT_BF16 = 2 } spt_dtype;
+
+typedef enum spt_algo {
+    SPT_ALGO_AUTO = 0,     /* library choice (tuned table, else the default heuristic) */
+    SPT_ALGO_ATOMIC = 1,   /* storage-order traversal, LDS-combined partial rows + atomics */
+    SPT_ALGO_PERMUTED = 2  /* mode-sorted traversal, wave segmented reduction */
+} spt_algo;
+
+/* Launch parameters of one MTTKRP.  Zero fields take the default.  The product
+ * lanes_per_nnz * cols_per_lane must cover R (lanes_per_nnz in {8,16,32,64}, cols_per_lane in
+ * {1,2,4}); nnz_per_wave is the number of entries one wavefront walks (a multiple of 64). */
+typedef struct spt_tune {
+    int32_t algo;
+    int32_t lanes_per_nnz;
+    int32_t cols_per_lane;
+    int32_t nnz_per_wave;
+} spt_tune;
+
+typedef struct spt_tensor spt_tensor;
+
+const char *spt_status_string(int status);
+int spt_version(void); /* major*10000 + minor*100 + patch */
+
+/* ---------------------------------------------------------------------------------------------
+ * Sparse tensor in coordinate (COO) format, Sec. 3: P entries, each a value x_i and subscripts
+ * (l_i1 .. l_id).  Duplicate subscripts are allowed and mean the sum of the entries (MTTKRP is
+ * linear in the entries); CP fit and the GCP loss assume distinct subscripts.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Workspace needed by a tensor of order d (2..5) with the given mode lengths, entry count and
+ * value dtype (SPT_F64 or SPT_F32).  It holds the packed entry records, one permutation and one
+ * sorted key array per mode (Sec. 5: d extra arrays of P ordinals), the radix-sort scratch and
+ * the status word.  Returns 0 for invalid arguments. */
+size_t spt_tensor_workspace_bytes(int d, const int64_t *dims, int64_t nnz, int vals_dtype);
+
+/* Builds a tensor handle.
+ *   out        receives the host-side handle (free with spt_tensor_destroy)
+ *   dims       host, d mode lengths I_m (1 .. 2^31-1)
+ *   subs       device, nnz x d int32 row-major subscripts; read only during this call's work
+ *   vals       device, nnz values of vals_dtype (SPT_F64 or SPT_F32); read only likewise
+ *   ws         device workspace of at least spt_tensor_workspace_bytes(), 256-byte aligned;
+ *              owned by the caller, must outlive the handle
+ * Enqueues the packing of (subs, vals) into the workspace; subscripts outside [0, I_m) are
+ * reported by spt_tensor_validate.  nnz may be 0. */
+int spt_tensor_create(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
+                      const int32_t *subs, const void *vals, int vals_dtype, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Synchronises `stream`; returns SPT_ERANGE (and the first offending entry index in *bad_entry
+ * when not NULL) if a subscript was out of range, else the pending device status. */
+int spt_tensor_validate(const spt_tensor *X, int64_t *bad_entry, void *stream);
+
+/* Synchronises `stream` and returns the device status word (then clears it). */
+int spt_tensor_status(const spt_tensor *X, void *stream);
+
+/* Builds the mode-`mode` permutation (mode = -1: every mode), Sec. 5: perm_n is the stable
+ * order of the entries by their mode-n subscript (ties in storage order) and skey_n the sorted
+ * subscripts.  Hand-written LSD radix sort, 8-bit digits.  Enqueued only. */
+int spt_tensor_permute(spt_tensor *X, int mode, void *stream);
+
+/* Device pointers of the mode's permutation and sorted keys (valid after spt_tensor_permute's
+ * work completes, until the handle is destroyed); SPT_ESTATE if the mode is not permuted. */
+int spt_tensor_perm(const spt_tensor *X, int mode, const int32_t **perm, const int32_t **skey);
+
+int spt_tensor_info(const spt_tensor *X, int *d, int64_t *dims, int64_t *nnz, int *vals_dtype);
+int spt_tensor_destroy(spt_tensor *X);
+
+/* ---------------------------------------------------------------------------------------------
+ * MTTKRP, eq. (mttkrp) of Sec. 3:
+ *   V(k, j) = lambda_j * sum_{i : l_in = k} x_i * prod_{m != n} A^(m)(l_im, j)
+ *   X        tensor handle (SPT_ALGO_PERMUTED needs spt_tensor_permute(mode) first)
+ *   mode     n, 0 <= n < d
+ *   R        rank, 1 .. 256
+ *   factors  host array of d device pointers, A^(m) is I_m x R row-major of fdtype; the entry
+ *            for m == n is not read and may be NULL
+ *   fdtype   SPT_F64 (needs F64 tensor values), SPT_F32 or SPT_BF16 (need F32 values)
+ *   lambda   device R doubles, or NULL for all ones
+ *   vals     device, NULL to use the tensor's values, else P replacement values in the tensor's
+ *            value dtype, in storage order (the GCP backward passes its derivative tensor here)
+ *   V        device I_n x R output, double for SPT_F64 factors, float otherwise; overwritten
+ *            (zeroed, then accumulated)
+ *   tune     NULL or launch parameters (see spt_tune)
+ * Products and accumulation run in FP64 for SPT_F64 and in FP32 otherwise (BF16 factors are
+ * widened to FP32 on load). */
+int spt_mttkrp(const spt_tensor *X, int mode, int R, const void *const *factors, int fdtype,
+               const double *lambda, const void *vals, void *V, const spt_tune *tune,
+               void *stream);
+
+/* The launch parameters spt_mttkrp uses for (X, mode, R, fdtype, algo) when tune is NULL. */
+int spt_mttkrp_default_tune(const spt_tensor *X, int mode, int R, int fdtype, int algo,
+                            spt_tune *out);
+
+/* ---------------------------------------------------------------------------------------------
+ * CP-ALS (Sec. 3 uses alternating least squares and defers the algorithm to Kolda & Bader).
+ * One mode update n:
+ *   V = MTTKRP(X, A, n, lambda = ones)
+ *   Gamma = Hadamard product of G_m, m != n            (FP64, R x R)
+ *   Gamma = L L^T (Cholesky; a pivot <= R * eps * max diag(Gamma) sets SPT_ESINGULAR)
+ *   row k of A^(n) solves A^(n)(k,:) Gamma = V(k,:)     (FP64 forward/back substitution)
+ *   lambda_j = ||A^(n)(:,j)||_2, columns with lambda_j > 0 divided by lambda_j, then stored in
+ *   fdtype (BF16: round to nearest even)
+ *   G_n = A^(n)^T A^(n) from the stored values         (FP64)
+ * factors: host array of d device pointers (I_m x R, fdtype), A^(n) overwritten.
+ * lambda: device R doubles (overwritten).  grams: device d x R x R doubles, G_m for every mode
+ * on entry (spt_cp_gram), G_n overwritten.  ws: device workspace of spt_cp_workspace_bytes().
+ * R must be <= 64. */
+size_t spt_cp_workspace_bytes(const spt_tensor *X, int R);
+
+int spt_cp_gram(int64_t I, int R, const void *A, int fdtype, double *G, void *ws,
+                size_t ws_bytes, void *stream);
+
+int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fdtype,
+                    double *lambda, double *grams, void *ws, size_t ws_bytes,
+                    const spt_tune *tune, void *stream);
+
+/* spt_cp_als_mode for n = 0 .. d-1. */
+int spt_cp_als_sweep(spt_tensor *X, int R, void *const *factors, int fdtype, double *lambda,
+                     double *grams, void *ws, size_t ws_bytes, const spt_tune *tune,
+                     void *stream);
+
+/* Fit of the model M = sum_j lambda_j a_j^(1) o ... o a_j^(d) (eq. (CP)) from the stored
+ * entries: fit = 1 - sqrt(max(0, ||X||^2 - 2<X,M> + ||M||^2)) / ||X|| with ||X||^2 and <X,M>
+ * summed over the entries in FP64 and ||M||^2 = lambda^T (Hadamard of all G_m) lambda.
+ * Synchronises `stream`; writes the fit to *fit (host) and, if parts != NULL, the three terms
+ * to parts[0..2] (host).  Returns a pending device status (e.g. SPT_ESINGULAR) if any. */
+int spt_cp_fit(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+               const double *lambda, const double *grams, void *ws, size_t ws_bytes,
+               double *fit, double *parts, void *stream);
+
+/* Model value of every stored entry, m_i = sum_j lambda_j prod_m A^(m)(l_im, j) (eq. (CP)).
+ * out: device P values, double for SPT_F64 factors, float otherwise.  lambda may be NULL. */
+int spt_model_values(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                     const double *lambda, void *out, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Generalized CP with the Poisson log-link loss (Sec. 7 names generalized CP, for count and
+ * binary data, as the next workload): f(x, m) = exp(m) - x m summed over the stored entries
+ * (nonzeros and sampled zeros), model m_i = sum_j prod_m A^(m)(l_im, j) (no weights lambda).
+ * fdtype SPT_F64 (tensor values F64; w, m, y double) or SPT_F32 (values F32; w, m, y float).
+ *   forward:  m (device P values, out), loss (device 1 double, out) = sum_i w_i f(x_i, m_i),
+ *             summed in FP64; ws: device scratch of at least 32 KiB, 256-byte aligned
+ *   backward: y_i = g w_i (exp(m_i) - x_i) into y (device P values, scratch), g = *gscale
+ *             (device double, the upstream gradient; NULL = 1), then grads[n] = MTTKRP(Y, A, n)
+ *             for every mode (host array of d device I_n x R buffers, double for F64 else float)
+ * w: device P weights or NULL (all ones).  R <= 64 for the forward pass. */
+int spt_gcp_poisson_forward(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                            const void *w, void *m, double *loss, void *ws, size_t ws_bytes,
+                            void *stream);
+int spt_gcp_poisson_backward(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                             const void *w, const void *m, const double *gscale, void *y,
+                             void *const *grads, const spt_tune *tune, void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Precision and measurement helpers
+ * ------------------------------------------------------------------------------------------- */
+
+/* FP32 -> BF16 bit patterns, round to nearest, ties to even; NaN stays a quiet NaN with its
+ * sign.  in: device n floats; out: device n uint16. */
+int spt_f32_to_bf16(const float *in, uint16_t *out, int64_t n, void *stream);
+
+/* STREAM-style triad a[i] = b[i] + s * c[i] over n floats (device), for measuring achievable
+ * HBM bandwidth. */
+int spt_stream_triad(float *a, const float *b, const float *c, float s, int64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,329 @@
+"""MI355X-native sparse COO tensor MTTKRP and CP-ALS (arXiv 1809.09175, Phipps & Kolda).
+
+Thin Python layer over libspt.so: torch supplies device memory and streams, every computation
+runs in the library's HIP kernels.  Nothing here computes MTTKRP, sorts or solves on the host.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (ALGO_ATOMIC, ALGO_AUTO, ALGO_PERMUTED, SPT_BF16, SPT_F32, SPT_F64, SptError,
+                   SptTune, SptUnavailable)
+
+__all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPPoissonLoss",
+           "default_tune", "to_bf16", "stream_triad", "SptError", "SptUnavailable",
+           "ALGO_AUTO", "ALGO_ATOMIC", "ALGO_PERMUTED", "dtype_code"]
+
+_ALGOS = {"auto": ALGO_AUTO, "atomic": ALGO_ATOMIC, "permuted": ALGO_PERMUTED,
+          ALGO_AUTO: ALGO_AUTO, ALGO_ATOMIC: ALGO_ATOMIC, ALGO_PERMUTED: ALGO_PERMUTED}
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def dtype_code(t) -> int:
+    """spt dtype of a factor tensor: float64, float32, or bfloat16 (BF16 bit patterns)."""
+    dt = t.dtype if isinstance(t, torch.Tensor) else t
+    if dt == torch.float64:
+        return SPT_F64
+    if dt == torch.float32:
+        return SPT_F32
+    if dt == torch.bfloat16:
+        return SPT_BF16
+    raise TypeError(f"unsupported factor dtype {dt}")
+
+
+def _dev_check(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA (HIP) tensor")
+
+
+def _tune(algo="auto", lanes=0, cols=0, chunk=0):
+    return SptTune(_ALGOS[algo], int(lanes), int(cols), int(chunk))
+
+
+class SparseTensor:
+    """COO tensor held by libspt: packed entry records plus per-mode permutations.
+
+    subs: (P, d) int32 CUDA tensor of 0-based subscripts; vals: (P,) float32/float64 CUDA tensor.
+    The library packs them into a workspace this object owns (a torch uint8 buffer)."""
+
+    def __init__(self, subs: torch.Tensor, vals: torch.Tensor, dims, stream=None):
+        lib = _lib.load()
+        _dev_check(subs, "subs")
+        _dev_check(vals, "vals")
+        if subs.dtype != torch.int32 or subs.dim() != 2:
+            raise ValueError("subs must be a (P, d) int32 tensor")
+        if vals.dtype not in (torch.float32, torch.float64) or vals.shape != (subs.shape[0],):
+            raise ValueError("vals must be (P,) float32 or float64")
+        self.d = int(subs.shape[1])
+        self.dims = tuple(int(x) for x in dims)
+        if len(self.dims) != self.d:
+            raise ValueError("dims must have d entries")
+        self.nnz = int(subs.shape[0])
+        self.device = subs.device
+        self.vdtype = SPT_F64 if vals.dtype == torch.float64 else SPT_F32
+        self.vals_dtype = vals.dtype
+        dims_arr = (ctypes.c_int64 * self.d)(*self.dims)
+        nbytes = lib.spt_tensor_workspace_bytes(self.d, dims_arr, self.nnz, self.vdtype)
+        if nbytes == 0:
+            raise ValueError("unsupported tensor shape (order must be 2..5, dims < 2^31)")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(lib.spt_tensor_create(ctypes.byref(h), self.d, dims_arr, self.nnz,
+                                             ctypes.c_void_p(subs.data_ptr()),
+                                             ctypes.c_void_p(vals.data_ptr()), self.vdtype,
+                                             ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                             _stream(stream)), "spt_tensor_create")
+        self._h = h
+        self._keep = (subs, vals)   # alive until the packing work has run
+
+    @property
+    def handle(self):
+        return self._h
+
+    def permute(self, mode: int = -1, stream=None):
+        _lib.check(_lib.load().spt_tensor_permute(self._h, int(mode), _stream(stream)),
+                   "spt_tensor_permute")
+        return self
+
+    def validate(self, stream=None):
+        bad = ctypes.c_int64(-1)
+        rc = _lib.load().spt_tensor_validate(self._h, ctypes.byref(bad), _stream(stream))
+        if rc != 0:
+            raise SptError(rc, f"validate (first bad entry {bad.value})")
+        self._keep = None
+        return self
+
+    def status(self, stream=None) -> int:
+        return _lib.load().spt_tensor_status(self._h, _stream(stream))
+
+    def perm(self, mode: int):
+        """(perm, skey) of a permuted mode, as int32 views into the workspace."""
+        p = ctypes.c_void_p()
+        k = ctypes.c_void_p()
+        _lib.check(_lib.load().spt_tensor_perm(self._h, int(mode), ctypes.byref(p),
+                                               ctypes.byref(k)), "spt_tensor_perm")
+        base = self.ws.data_ptr()
+        n = self.nnz
+        out = []
+        for q in (p.value, k.value):
+            off = (q or base) - base
+            out.append(self.ws[off:off + 4 * n].view(torch.int32))
+        return out[0], out[1]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().spt_tensor_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_tune(X: SparseTensor, mode: int, R: int, fdtype, algo="auto") -> dict:
+    t = SptTune()
+    _lib.check(_lib.load().spt_mttkrp_default_tune(X.handle, int(mode), int(R),
+                                                   dtype_code(fdtype), _ALGOS[algo],
+                                                   ctypes.byref(t)), "default_tune")
+    return {"algo": t.algo, "lanes": t.lanes_per_nnz, "cols": t.cols_per_lane,
+            "chunk": t.nnz_per_wave}
+
+
+def _factor_ptrs(factors, skip=-1):
+    ptrs = []
+    for m, f in enumerate(factors):
+        if m == skip and f is None:
+            ptrs.append(None)
+            continue
+        _dev_check(f, f"factor {m}")
+        ptrs.append(f.data_ptr())
+    return _lib.ptr_array(ptrs)
+
+
+def mttkrp(X: SparseTensor, factors, mode: int, lam=None, algo="auto", lanes=0, cols=0,
+           chunk=0, vals=None, out=None, stream=None):
+    """Mode-`mode` MTTKRP (eq. (mttkrp)).  factors: d CUDA tensors (I_m, R) of one dtype
+    (float64, float32 or bfloat16); lam: optional (R,) float64.  Returns V (I_n, R): float64
+    for float64 factors, float32 otherwise."""
+    lib = _lib.load()
+    ref = factors[0] if factors[0] is not None else factors[1]
+    R = int(ref.shape[1])
+    fd = dtype_code(ref)
+    vdt = torch.float64 if fd == SPT_F64 else torch.float32
+    if out is None:
+        out = torch.empty((X.dims[mode], R), dtype=vdt, device=X.device)
+    _dev_check(out, "out")
+    if lam is not None:
+        _dev_check(lam, "lam")
+        if lam.dtype != torch.float64:
+            raise ValueError("lam must be float64")
+    if vals is not None:
+        _dev_check(vals, "vals")
+    tune = _tune(algo, lanes, cols, chunk)
+    _lib.check(lib.spt_mttkrp(X.handle, int(mode), R, _factor_ptrs(factors, mode), fd,
+                              ctypes.c_void_p(lam.data_ptr()) if lam is not None else None,
+                              ctypes.c_void_p(vals.data_ptr()) if vals is not None else None,
+                              ctypes.c_void_p(out.data_ptr()), ctypes.byref(tune),
+                              _stream(stream)), "spt_mttkrp")
+    return out
+
+
+def to_bf16(x: torch.Tensor, stream=None) -> torch.Tensor:
+    """FP32 -> BF16 (round to nearest even) with the library's kernel."""
+    _dev_check(x, "x")
+    if x.dtype != torch.float32:
+        raise ValueError("x must be float32")
+    out = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
+    _lib.check(_lib.load().spt_f32_to_bf16(ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), x.numel(),
+                                           _stream(stream)), "spt_f32_to_bf16")
+    return out
+
+
+def stream_triad(a, b, c, s=3.0, stream=None):
+    _lib.check(_lib.load().spt_stream_triad(ctypes.c_void_p(a.data_ptr()),
+                                            ctypes.c_void_p(b.data_ptr()),
+                                            ctypes.c_void_p(c.data_ptr()), float(s), a.numel(),
+                                            _stream(stream)), "spt_stream_triad")
+
+
+# ------------------------------------------------------------------------------------ CP-ALS
+
+class CPState:
+    """Kruskal tensor state of CP-ALS: factors (d CUDA tensors, I_m x R, float64/float32/
+    bfloat16), weights lam (R float64) and the Gram matrices (d x R x R float64)."""
+
+    def __init__(self, X: SparseTensor, factors, stream=None):
+        lib = _lib.load()
+        self.X = X
+        self.factors = [f.contiguous() for f in factors]
+        for f in self.factors:
+            _dev_check(f, "factor")
+        self.R = int(self.factors[0].shape[1])
+        self.fdtype = dtype_code(self.factors[0])
+        dev = X.device
+        self.lam = torch.ones(self.R, dtype=torch.float64, device=dev)
+        self.grams = torch.empty((X.d, self.R, self.R), dtype=torch.float64, device=dev)
+        nbytes = lib.spt_cp_workspace_bytes(X.handle, self.R)
+        if nbytes == 0:
+            raise SptError(_lib.SPT_EUNSUPPORTED, "spt_cp_workspace_bytes (R must be <= 64)")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        for m, f in enumerate(self.factors):
+            _lib.check(lib.spt_cp_gram(int(f.shape[0]), self.R, ctypes.c_void_p(f.data_ptr()),
+                                       self.fdtype,
+                                       ctypes.c_void_p(self.grams[m].data_ptr()),
+                                       ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                       _stream(stream)), "spt_cp_gram")
+
+    def _fptrs(self):
+        return _lib.ptr_array([f.data_ptr() for f in self.factors])
+
+    def mode_update(self, n: int, algo="auto", lanes=0, cols=0, chunk=0, stream=None):
+        tune = _tune(algo, lanes, cols, chunk)
+        _lib.check(_lib.load().spt_cp_als_mode(
+            self.X.handle, int(n), self.R, self._fptrs(), self.fdtype,
+            ctypes.c_void_p(self.lam.data_ptr()), ctypes.c_void_p(self.grams.data_ptr()),
+            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(tune),
+            _stream(stream)), "spt_cp_als_mode")
+
+    def sweep(self, algo="auto", stream=None):
+        tune = _tune(algo)
+        _lib.check(_lib.load().spt_cp_als_sweep(
+            self.X.handle, self.R, self._fptrs(), self.fdtype,
+            ctypes.c_void_p(self.lam.data_ptr()), ctypes.c_void_p(self.grams.data_ptr()),
+            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(tune),
+            _stream(stream)), "spt_cp_als_sweep")
+
+    def fit(self, return_parts=False, stream=None):
+        """Synchronising: fit of the current model from the stored entries (FP64)."""
+        f = ctypes.c_double()
+        parts = (ctypes.c_double * 3)()
+        _lib.check(_lib.load().spt_cp_fit(
+            self.X.handle, self.R, self._fptrs(), self.fdtype,
+            ctypes.c_void_p(self.lam.data_ptr()), ctypes.c_void_p(self.grams.data_ptr()),
+            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(f), parts,
+            _stream(stream)), "spt_cp_fit")
+        return (f.value, list(parts)) if return_parts else f.value
+
+
+def cp_als(X: SparseTensor, factors, iters=10, algo="auto", tol=None):
+    """Run CP-ALS sweeps from the given initial factors (updated in place).  Returns the state
+    and the fit after every sweep."""
+    st = CPState(X, factors)
+    fits = []
+    for _ in range(iters):
+        st.sweep(algo)
+        fits.append(st.fit())
+        if tol is not None and len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
+            break
+    return st, fits
+
+
+def model_values(X: SparseTensor, factors, lam=None, stream=None):
+    fd = dtype_code(factors[0])
+    out = torch.empty(X.nnz, dtype=torch.float64 if fd == SPT_F64 else torch.float32,
+                      device=X.device)
+    _lib.check(_lib.load().spt_model_values(
+        X.handle, int(factors[0].shape[1]), _factor_ptrs(factors), fd,
+        ctypes.c_void_p(lam.data_ptr()) if lam is not None else None,
+        ctypes.c_void_p(out.data_ptr()), _stream(stream)), "spt_model_values")
+    return out
+
+
+# ----------------------------------------------------------------------- generalized CP (GCP)
+
+class GCPPoissonLoss(torch.autograd.Function):
+    """loss = sum_i w_i (exp(m_i) - x_i m_i) over the tensor's stored entries (nonzeros and
+    sampled zeros), m_i = sum_j prod_m A^(m)(l_im, j).  Forward and backward run in libspt; the
+    backward is one MTTKRP per mode of the derivative tensor y_i = w_i (exp(m_i) - x_i).
+
+    Usage: loss = GCPPoissonLoss.apply(X, w, *factors)   (w may be None)."""
+
+    @staticmethod
+    def forward(ctx, X, w, *factors):
+        lib = _lib.load()
+        fd = dtype_code(factors[0])
+        if fd == SPT_BF16:
+            raise TypeError("GCP factors must be float32 or float64")
+        R = int(factors[0].shape[1])
+        vdt = torch.float64 if fd == SPT_F64 else torch.float32
+        facs = [f.detach().contiguous() for f in factors]
+        m = torch.empty(X.nnz, dtype=vdt, device=X.device)
+        loss = torch.empty((), dtype=torch.float64, device=X.device)
+        ws = torch.empty(32768, dtype=torch.uint8, device=X.device)
+        _lib.check(lib.spt_gcp_poisson_forward(
+            X.handle, R, _factor_ptrs(facs), fd,
+            ctypes.c_void_p(w.data_ptr()) if w is not None else None,
+            ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "spt_gcp_poisson_forward")
+        ctx.X = X
+        ctx.w = w
+        ctx.fd = fd
+        ctx.save_for_backward(m, *facs)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gout):
+        m, *facs = ctx.saved_tensors
+        X = ctx.X
+        R = int(facs[0].shape[1])
+        g = gout.detach().to(torch.float64).contiguous()
+        y = torch.empty_like(m)
+        grads = [torch.empty_like(f) for f in facs]
+        _lib.check(_lib.load().spt_gcp_poisson_backward(
+            X.handle, R, _factor_ptrs(facs), ctx.fd,
+            ctypes.c_void_p(ctx.w.data_ptr()) if ctx.w is not None else None,
+            ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+            ctypes.c_void_p(y.data_ptr()), _lib.ptr_array([t.data_ptr() for t in grads]), None,
+            _stream()), "spt_gcp_poisson_backward")
+        return (None, None, *grads)

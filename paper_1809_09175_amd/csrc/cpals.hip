@@ -1,0 +1,624 @@
+// CP-ALS on the GPU (Sec. 3 defers the algorithm to Kolda & Bader; this is the textbook update):
+// Gram matrices, their Hadamard product, an R x R Cholesky factorisation, row-parallel
+// triangular solves, column normalisation, and the fit computed from the stored entries.
+// All of it in FP64; factors are stored in FP64, FP32 or BF16.
+#include "mttkrp_kernels.h"
+
+namespace spt {
+
+constexpr int kCpMaxR = 64;
+constexpr int kGramRows = 64;       // rows staged per tile in the Gram kernel
+constexpr int kMaxPartBlocks = 1024;
+
+struct CpWs {
+    size_t V, Y, L, gpart, cpart, misc, total;
+};
+
+static CpWs cp_layout(int64_t Imax, int R) {
+    CpWs w;
+    size_t o = 0;
+    w.V = o;
+    o += align256((size_t)Imax * R * 8);
+    w.Y = o;
+    o += align256((size_t)Imax * R * 8);
+    w.L = o;
+    o += align256((size_t)R * R * 8);
+    w.gpart = o;
+    o += align256((size_t)kMaxPartBlocks * R * R * 8);
+    w.cpart = o;  // Y^T Y
+    o += align256((size_t)R * R * 8);
+    w.misc = o;
+    o += align256(64 * 8);
+    w.total = o;
+    return w;
+}
+
+template <class FT>
+__device__ __forceinline__ double load_f64(const FT *p) {
+    if constexpr (sizeof(FT) == 2) return (double)bf16_bits_to_f32(*reinterpret_cast<const uint16_t *>(p));
+    else return (double)*p;
+}
+
+template <class FT>
+__device__ __forceinline__ void store_from_f64(FT *p, double v) {
+    if constexpr (sizeof(FT) == 2) *reinterpret_cast<uint16_t *>(p) = f32_to_bf16_rne((float)v);
+    else *p = (FT)v;
+}
+
+// deterministic block sum of one double per thread (result valid in every thread)
+__device__ double block_sum_f64(double v) {
+    __shared__ double red[kBlock / kWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) s += red[w];
+    return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Gram matrices  G = A^T A  (FP64).  Optionally normalises and stores the factor first.
+// ------------------------------------------------------------------------------------------
+
+// Tile of rows -> per-block partial Gram.  With NORMALIZE, the tile comes from the FP64 solve
+// output Y: a = y / lambda (columns with lambda > 0), stored to A in FT, and the Gram uses the
+// stored (rounded) values.
+template <class FT, bool NORMALIZE>
+__global__ __launch_bounds__(kBlock) void k_gram_partial(const FT *__restrict__ Ain,
+                                                         const double *__restrict__ Y,
+                                                         const double *__restrict__ lambda,
+                                                         FT *__restrict__ Aout, int64_t I, int R,
+                                                         double *__restrict__ gpart) {
+    __shared__ double tile[kGramRows][kCpMaxR + 1];
+    const int tid = threadIdx.x;
+    const int RR = R * R;
+    double acc[kCpMaxR * kCpMaxR / kBlock];  // up to 16 entries of G per thread
+#pragma unroll
+    for (int e = 0; e < kCpMaxR * kCpMaxR / kBlock; ++e) acc[e] = 0.0;
+    for (int64_t r0 = (int64_t)blockIdx.x * kGramRows; r0 < I; r0 += (int64_t)gridDim.x * kGramRows) {
+        const int nrows = (I - r0 < kGramRows) ? (int)(I - r0) : kGramRows;
+        for (int e = tid; e < kGramRows * R; e += kBlock) {
+            const int rr = e / R, c = e - rr * R;
+            double v = 0.0;
+            if (rr < nrows) {
+                const int64_t idx = (r0 + rr) * R + c;
+                if constexpr (NORMALIZE) {
+                    double y = Y[idx];
+                    const double l = lambda[c];
+                    if (l > 0.0) y = y / l;
+                    store_from_f64<FT>(Aout + idx, y);
+                    v = load_f64<FT>(Aout + idx);
+                } else {
+                    v = load_f64<FT>(Ain + idx);
+                }
+            }
+            tile[rr][c] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kCpMaxR * kCpMaxR / kBlock; ++e) {
+            const int ab = tid + e * kBlock;
+            if (ab < RR) {
+                const int a = ab / R, b = ab - a * R;
+                double s = acc[e];
+                for (int rr = 0; rr < nrows; ++rr) s += tile[rr][a] * tile[rr][b];
+                acc[e] = s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < kCpMaxR * kCpMaxR / kBlock; ++e) {
+        const int ab = tid + e * kBlock;
+        if (ab < RR) gpart[(int64_t)blockIdx.x * RR + ab] = acc[e];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__ part, int nblk,
+                                                      int len, double *__restrict__ out) {
+    for (int i = threadIdx.x; i < len; i += kBlock) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * len + i];
+        out[i] = s;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Hadamard product of the other modes' Grams and its Cholesky factor (one workgroup).  Same
+// column-by-column order as the textbook algorithm; no FMA contraction here so the factor
+// follows the plain definition's rounding.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restrict__ grams, int d,
+                                                          int n, int R, double *__restrict__ L,
+                                                          SptStatusBlock *st) {
+#pragma clang fp contract(off)
+    __shared__ double S[kCpMaxR][kCpMaxR];
+    __shared__ double Lc[kCpMaxR][kCpMaxR];
+    __shared__ double lcc_s;
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    for (int ab = tid; ab < R * R; ab += kBlock) {
+        double g = 1.0;
+        for (int m = 0; m < d; ++m)
+            if (m != n) g *= grams[(int64_t)m * R * R + ab];
+        S[ab / R][ab % R] = g;
+        Lc[ab / R][ab % R] = 0.0;
+    }
+    __syncthreads();
+    double maxdiag = 0.0;
+    for (int k = 0; k < R; ++k) maxdiag = S[k][k] > maxdiag ? S[k][k] : maxdiag;
+    const double tol = (double)R * 2.220446049250313e-16 * maxdiag;
+    for (int c = 0; c < R; ++c) {
+        if (tid == 0) {
+            double piv = S[c][c];
+            for (int k = 0; k < c; ++k) piv -= Lc[c][k] * Lc[c][k];
+            if (!(piv > tol)) {
+                bad = 1;
+                piv = 1.0;  // keep the factor finite; the status word reports the failure
+            }
+            lcc_s = sqrt(piv);
+            Lc[c][c] = lcc_s;
+        }
+        __syncthreads();
+        const double lcc = lcc_s;
+        for (int r = c + 1 + tid; r < R; r += kBlock) {
+            double s = S[r][c];
+            for (int k = 0; k < c; ++k) s -= Lc[r][k] * Lc[c][k];
+            Lc[r][c] = s / lcc;
+        }
+        __syncthreads();
+    }
+    for (int ab = tid; ab < R * R; ab += kBlock) L[ab] = Lc[ab / R][ab % R];
+    if (tid == 0 && bad) raise_status(st, SPT_ESINGULAR);
+}
+
+// ------------------------------------------------------------------------------------------
+// Row solves: row k of the unnormalised factor solves  a Gamma = v  with Gamma = L L^T
+// (forward substitution with L, then back substitution with L^T), one thread per row, in the
+// textbook order.  The column 2-norms come afterwards from the diagonal of Y^T Y.
+// ------------------------------------------------------------------------------------------
+template <int RMAX, class VT>
+__global__ __launch_bounds__(kBlock) void k_solve_rows(const VT *__restrict__ V, int64_t I, int R,
+                                                       const double *__restrict__ Lg,
+                                                       double *__restrict__ Y) {
+#pragma clang fp contract(off)
+    __shared__ double L[RMAX * RMAX];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < R * R; e += kBlock) L[e] = Lg[e];
+    __syncthreads();
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + tid; k < I; k += (int64_t)gridDim.x * kBlock) {
+        double a[RMAX];
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c) a[c] = (c < R) ? (double)V[k * R + c] : 0.0;
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c) {
+            if (c < R) {
+                double s = a[c];
+#pragma unroll
+                for (int q = 0; q < c; ++q) s -= L[c * R + q] * a[q];
+                a[c] = s / L[c * R + c];
+            }
+        }
+#pragma unroll
+        for (int c = RMAX - 1; c >= 0; --c) {
+            if (c < R) {
+                double s = a[c];
+#pragma unroll
+                for (int q = c + 1; q < RMAX; ++q)
+                    if (q < R) s -= L[q * R + c] * a[q];
+                a[c] = s / L[c * R + c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c)
+            if (c < R) Y[k * R + c] = a[c];
+    }
+}
+
+// lambda_j = sqrt((Y^T Y)_jj)
+__global__ void k_norms_from_gram(const double *__restrict__ GY, int R, double *__restrict__ lambda) {
+    for (int c = threadIdx.x; c < R; c += blockDim.x) lambda[c] = sqrt(GY[c * R + c]);
+}
+
+// ------------------------------------------------------------------------------------------
+// Fit / model values / GCP forward: one pass over the stored entries in storage order.
+// Lane groups of G lanes evaluate one entry: each lane forms lambda_j prod_m A^(m)(l_m, j) for
+// its column, the group sums over columns.
+// ------------------------------------------------------------------------------------------
+enum { KIND_FIT = 0, KIND_VALUES = 1, KIND_GCP = 2 };
+
+template <int D, int G, class FT, class VT, class CT, int KIND>
+__global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, int64_t P, int R,
+                                                  FactorSet<FT> A, const double *__restrict__ lambda,
+                                                  const CT *__restrict__ w, void *__restrict__ mout,
+                                                  double *__restrict__ part, int chunk) {
+    constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
+    constexpr int U = 4;
+    __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane / G, gl = lane % G;
+    const bool colok = gl < R;
+    const CT lam = (lambda != nullptr && colok) ? (CT)lambda[gl] : (CT)1;
+    double s0acc = 0.0, s1acc = 0.0;
+    const int64_t nchunks = ceil_div(P, chunk);
+    for (int64_t ch = (int64_t)blockIdx.x * (kBlock / kWave) + wave; ch < nchunks;
+         ch += (int64_t)gridDim.x * (kBlock / kWave)) {
+        const int64_t c0 = ch * chunk;
+        const int len = (int)((c0 + chunk < P) ? chunk : P - c0);
+        for (int b = 0; b < len; b += kWave) {
+            if (b + lane < len) {
+                const int4 *r = rec + (c0 + b + lane) * RQ;
+                s_rec[wave][lane * RQ] = r[0];
+                if constexpr (RQ == 2) s_rec[wave][lane * RQ + 1] = r[1];
+            }
+            wave_sync();
+            int cnt = len - b - g * G;
+            cnt = cnt < G ? cnt : G;
+            for (int u0 = 0; u0 < cnt; u0 += U) {
+                CT t[U];
+                VT x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    t[u] = 0;
+                    x[u] = 0;
+                    if (u0 + u < cnt) {
+                        int wv[RW];
+                        const int4 *q = &s_rec[wave][(g * G + u0 + u) * RQ];
+                        int4 a = q[0];
+                        wv[0] = a.x; wv[1] = a.y; wv[2] = a.z; wv[3] = a.w;
+                        if constexpr (RQ == 2) {
+                            int4 bq = q[1];
+                            wv[4] = bq.x; wv[5] = bq.y; wv[6] = bq.z; wv[7] = bq.w;
+                        }
+                        x[u] = rec_value<VT, RW>(wv);
+                        if (colok) {
+                            CT p = lam;
+#pragma unroll
+                            for (int m = 0; m < D; ++m) {
+                                CT f[1];
+                                load_cols<FT, 1, CT>(A.p[m] + (int64_t)wv[m] * R + gl, f);
+                                p *= f[0];
+                            }
+                            t[u] = p;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    CT m = t[u];
+#pragma unroll
+                    for (int o = G / 2; o > 0; o >>= 1) m += __shfl_xor(m, o, G);
+                    if (u0 + u < cnt && gl == 0) {
+                        const int64_t i = c0 + b + g * G + u0 + u;
+                        if constexpr (KIND == KIND_FIT) {
+                            const double xv = (double)x[u];
+                            s0acc += xv * xv;
+                            s1acc += xv * (double)m;
+                        } else if constexpr (KIND == KIND_VALUES) {
+                            static_cast<CT *>(mout)[i] = m;
+                        } else {
+                            static_cast<CT *>(mout)[i] = m;
+                            const double wi = (w != nullptr) ? (double)w[i] : 1.0;
+                            s0acc += wi * (exp((double)m) - (double)x[u] * (double)m);
+                        }
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+    if constexpr (KIND != KIND_VALUES) {
+        const double a0 = block_sum_f64(s0acc);
+        const double a1 = block_sum_f64(s1acc);
+        if (tid == 0) {
+            part[2 * blockIdx.x] = a0;
+            part[2 * blockIdx.x + 1] = a1;
+        }
+    }
+}
+
+// fit = 1 - sqrt(max(0, xx - 2 xm + mm)) / sqrt(xx),  mm = lambda^T (Hadamard of all G) lambda
+__global__ __launch_bounds__(kBlock) void k_fit_final(const double *__restrict__ part, int nblk,
+                                                      const double *__restrict__ lambda,
+                                                      const double *__restrict__ grams, int d,
+                                                      int R, double *__restrict__ out) {
+    double xx = 0.0, xm = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        xx += part[2 * b];
+        xm += part[2 * b + 1];
+    }
+    double mm = 0.0;
+    for (int ab = threadIdx.x; ab < R * R; ab += kBlock) {
+        const int a = ab / R, b = ab - a * R;
+        double g = 1.0;
+        for (int m = 0; m < d; ++m) g *= grams[(int64_t)m * R * R + ab];
+        const double la = lambda ? lambda[a] : 1.0, lb = lambda ? lambda[b] : 1.0;
+        mm += la * g * lb;
+    }
+    xx = block_sum_f64(xx);
+    xm = block_sum_f64(xm);
+    mm = block_sum_f64(mm);
+    if (threadIdx.x == 0) {
+        double r2 = xx - 2.0 * xm + mm;
+        if (r2 < 0.0) r2 = 0.0;
+        out[0] = 1.0 - sqrt(r2) / sqrt(xx);
+        out[1] = xx;
+        out[2] = xm;
+        out[3] = mm;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_loss_final(const double *__restrict__ part, int nblk,
+                                                       double *__restrict__ loss) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) s += part[2 * b];
+    s = block_sum_f64(s);
+    if (threadIdx.x == 0) *loss = s;
+}
+
+// ------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------
+
+static int group_for(int R) {
+    int G = 8;
+    while (G < R) G <<= 1;
+    return G;
+}
+
+template <int D, class FT, class VT, class CT, int KIND>
+static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
+                          const double *lambda, const CT *w, void *mout, double *part,
+                          int *nblk_out, hipStream_t s) {
+    const int chunk = 2048;
+    int64_t nchunks = ceil_div(X->P, chunk);
+    int64_t nblk = ceil_div(nchunks, kBlock / kWave);
+    if (nblk > 2048) nblk = 2048;
+    if (nblk < 1) nblk = 1;
+    *nblk_out = (int)nblk;
+    const int G = group_for(R);
+#define SPT_MODEL_G(GG)                                                                       \
+    case GG:                                                                                  \
+        hipLaunchKernelGGL((k_model<D, GG, FT, VT, CT, KIND>), dim3((unsigned)nblk), dim3(kBlock), \
+                           0, s, X->rec, X->P, R, A, lambda, w, mout, part, chunk);          \
+        break;
+    switch (G) {
+        SPT_MODEL_G(8)
+        SPT_MODEL_G(16)
+        SPT_MODEL_G(32)
+        SPT_MODEL_G(64)
+        default: return SPT_EUNSUPPORTED;
+    }
+#undef SPT_MODEL_G
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+template <class FT, class VT, class CT, int KIND>
+int launch_model(const spt_tensor *X, int R, const void *const *factors, const double *lambda,
+                 const CT *w, void *mout, double *part, int *nblk, hipStream_t s) {
+    FactorSet<FT> A{};
+    for (int m = 0; m < X->d; ++m) A.p[m] = static_cast<const FT *>(factors[m]);
+    switch (X->d) {
+        case 2: return launch_model_d<2, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
+        case 3: return launch_model_d<3, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
+        case 4: return launch_model_d<4, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
+        case 5: return launch_model_d<5, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
+        default: return SPT_EUNSUPPORTED;
+    }
+}
+
+static int64_t max_dim(const spt_tensor *X) {
+    int64_t m = 1;
+    for (int i = 0; i < X->d; ++i) m = X->dims[i] > m ? X->dims[i] : m;
+    return m;
+}
+
+static int gram_blocks(int64_t I) {
+    int64_t b = ceil_div(I, kGramRows);
+    if (b > kMaxPartBlocks) b = kMaxPartBlocks;
+    return (int)(b < 1 ? 1 : b);
+}
+
+template <class FT, bool NORM>
+static int launch_gram(const FT *Ain, const double *Y, const double *lambda, FT *Aout, int64_t I,
+                       int R, double *gpart, double *G, hipStream_t s) {
+    const int nb = gram_blocks(I);
+    hipLaunchKernelGGL((k_gram_partial<FT, NORM>), dim3(nb), dim3(kBlock), 0, s, Ain, Y, lambda,
+                       Aout, I, R, gpart);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, s, gpart, nb, R * R, G);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+static int gram_any(int fdtype, const void *Ain, const double *Y, const double *lambda,
+                    void *Aout, int64_t I, int R, double *gpart, double *G, bool norm,
+                    hipStream_t s) {
+    switch (fdtype) {
+        case SPT_F64:
+            return norm ? launch_gram<double, true>(nullptr, Y, lambda, (double *)Aout, I, R, gpart, G, s)
+                        : launch_gram<double, false>((const double *)Ain, nullptr, nullptr, nullptr, I, R, gpart, G, s);
+        case SPT_F32:
+            return norm ? launch_gram<float, true>(nullptr, Y, lambda, (float *)Aout, I, R, gpart, G, s)
+                        : launch_gram<float, false>((const float *)Ain, nullptr, nullptr, nullptr, I, R, gpart, G, s);
+        case SPT_BF16:
+            return norm ? launch_gram<uint16_t, true>(nullptr, Y, lambda, (uint16_t *)Aout, I, R, gpart, G, s)
+                        : launch_gram<uint16_t, false>((const uint16_t *)Ain, nullptr, nullptr, nullptr, I, R, gpart, G, s);
+        default: return SPT_EINVAL;
+    }
+}
+
+template <class VT>
+static int launch_solve(const VT *V, int64_t I, int R, const double *L, double *Y, hipStream_t s) {
+    int64_t nb = ceil_div(I, kBlock);
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    if (R <= 16)
+        hipLaunchKernelGGL((k_solve_rows<16, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
+    else if (R <= 32)
+        hipLaunchKernelGGL((k_solve_rows<32, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
+    else
+        hipLaunchKernelGGL((k_solve_rows<64, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+}  // namespace spt
+
+using namespace spt;
+
+extern "C" {
+
+size_t spt_cp_workspace_bytes(const spt_tensor *X, int R) {
+    if (X == nullptr || R < 1 || R > kCpMaxR) return 0;
+    return cp_layout(max_dim(X), R).total;
+}
+
+int spt_cp_gram(int64_t I, int R, const void *A, int fdtype, double *G, void *ws,
+                size_t ws_bytes, void *stream) {
+    if (I < 1 || R < 1 || R > kCpMaxR || A == nullptr || G == nullptr || ws == nullptr)
+        return SPT_EINVAL;
+    if (ws_bytes < (size_t)kMaxPartBlocks * R * R * 8 || ((uintptr_t)ws & 255u))
+        return SPT_EWORKSPACE;
+    return gram_any(fdtype, A, nullptr, nullptr, nullptr, I, R, static_cast<double *>(ws), G,
+                    false, static_cast<hipStream_t>(stream));
+}
+
+int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fdtype,
+                    double *lambda, double *grams, void *ws, size_t ws_bytes,
+                    const spt_tune *tune, void *stream) {
+    if (X == nullptr || mode < 0 || mode >= X->d || R < 1 || lambda == nullptr ||
+        grams == nullptr || factors == nullptr)
+        return SPT_EINVAL;
+    if (R > kCpMaxR) return SPT_EUNSUPPORTED;
+    for (int m = 0; m < X->d; ++m)
+        if (factors[m] == nullptr) return SPT_EINVAL;
+    const CpWs L = cp_layout(max_dim(X), R);
+    if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < L.total) return SPT_EWORKSPACE;
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    void *V = w + L.V;
+    double *Y = reinterpret_cast<double *>(w + L.Y);
+    double *Lf = reinterpret_cast<double *>(w + L.L);
+    double *gpart = reinterpret_cast<double *>(w + L.gpart);
+    double *GY = reinterpret_cast<double *>(w + L.cpart);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t I = X->dims[mode];
+
+    int rc = check_mttkrp_args(X, mode, R, (const void *const *)factors, fdtype, V);
+    if (rc) return rc;
+    spt_tune t;
+    rc = resolve_tune(X, mode, R, fdtype, tune, &t);
+    if (rc) return rc;
+    if (t.algo == SPT_ALGO_PERMUTED && !X->permuted[mode]) return SPT_ESTATE;
+    // V = MTTKRP with the other (normalised) factors and unit weights
+    rc = launch_mttkrp(X, mode, R, (const void *const *)factors, fdtype, nullptr, nullptr, V, t, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_hadamard_chol, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R, Lf,
+                       X->status);
+    SPT_LAUNCH_CHECK();
+    rc = (fdtype == SPT_F64) ? launch_solve<double>((const double *)V, I, R, Lf, Y, s)
+                             : launch_solve<float>((const float *)V, I, R, Lf, Y, s);
+    if (rc) return rc;
+    // column norms from the diagonal of Y^T Y (the Gram routine on the FP64 solution)
+    rc = launch_gram<double, false>(Y, nullptr, nullptr, nullptr, I, R, gpart, GY, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_norms_from_gram, dim3(1), dim3(64), 0, s, GY, R, lambda);
+    SPT_LAUNCH_CHECK();
+    return gram_any(fdtype, nullptr, Y, lambda, factors[mode], I, R, gpart,
+                    grams + (size_t)mode * R * R, true, s);
+}
+
+int spt_cp_als_sweep(spt_tensor *X, int R, void *const *factors, int fdtype, double *lambda,
+                     double *grams, void *ws, size_t ws_bytes, const spt_tune *tune,
+                     void *stream) {
+    if (X == nullptr) return SPT_EINVAL;
+    for (int n = 0; n < X->d; ++n) {
+        int rc = spt_cp_als_mode(X, n, R, factors, fdtype, lambda, grams, ws, ws_bytes, tune, stream);
+        if (rc) return rc;
+    }
+    return SPT_OK;
+}
+
+int spt_cp_fit(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+               const double *lambda, const double *grams, void *ws, size_t ws_bytes,
+               double *fit, double *parts, void *stream) {
+    if (X == nullptr || R < 1 || R > kCpMaxR || grams == nullptr || fit == nullptr)
+        return SPT_EINVAL;
+    int rc = check_factors(X, -1, factors);
+    if (rc) return rc;
+    const CpWs L = cp_layout(max_dim(X), R);
+    if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < L.total) return SPT_EWORKSPACE;
+    if ((fdtype == SPT_F64) != (X->vdtype == SPT_F64)) return SPT_EUNSUPPORTED;
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    double *part = reinterpret_cast<double *>(w + L.gpart);
+    double *out = reinterpret_cast<double *>(w + L.misc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int nblk = 0;
+    switch (fdtype) {
+        case SPT_F64:
+            rc = launch_model<double, double, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
+            break;
+        case SPT_F32:
+            rc = launch_model<float, float, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
+            break;
+        case SPT_BF16:
+            rc = launch_model<uint16_t, float, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
+            break;
+        default: return SPT_EINVAL;
+    }
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(kBlock), 0, s, part, nblk, lambda, grams, X->d,
+                       R, out);
+    SPT_LAUNCH_CHECK();
+    double h[4];
+    SPT_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+    *fit = h[0];
+    if (parts) {
+        parts[0] = h[1];
+        parts[1] = h[2];
+        parts[2] = h[3];
+    }
+    return spt_tensor_status(X, stream);
+}
+
+int spt_model_values(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                     const double *lambda, void *out, void *stream) {
+    if (X == nullptr || R < 1 || R > kCpMaxR || out == nullptr) return SPT_EINVAL;
+    int rc = check_factors(X, -1, factors);
+    if (rc) return rc;
+    if ((fdtype == SPT_F64) != (X->vdtype == SPT_F64)) return SPT_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int nblk = 0;
+    switch (fdtype) {
+        case SPT_F64:
+            return launch_model<double, double, double, KIND_VALUES>(X, R, factors, lambda, nullptr, out, nullptr, &nblk, s);
+        case SPT_F32:
+            return launch_model<float, float, float, KIND_VALUES>(X, R, factors, lambda, nullptr, out, nullptr, &nblk, s);
+        case SPT_BF16:
+            return launch_model<uint16_t, float, float, KIND_VALUES>(X, R, factors, lambda, nullptr, out, nullptr, &nblk, s);
+        default: return SPT_EINVAL;
+    }
+}
+
+}  // extern "C"
+
+// GCP forward reuses k_model; defined here so the loss reduction kernel stays local.
+namespace spt {
+int gcp_forward_impl(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                     const void *w, void *m, double *loss, double *part, hipStream_t s) {
+    int nblk = 0;
+    int rc;
+    if (fdtype == SPT_F64)
+        rc = launch_model<double, double, double, KIND_GCP>(X, R, factors, nullptr,
+                                                           static_cast<const double *>(w), m, part, &nblk, s);
+    else
+        rc = launch_model<float, float, float, KIND_GCP>(X, R, factors, nullptr,
+                                                        static_cast<const float *>(w), m, part, &nblk, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kBlock), 0, s, part, nblk, loss);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+}  // namespace spt

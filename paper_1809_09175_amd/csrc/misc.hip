@@ -1,0 +1,60 @@
+// Precision and measurement helpers: FP32 -> BF16 rounding and a STREAM-style triad.
+#include "spt_internal.h"
+
+namespace spt {
+
+__global__ __launch_bounds__(kBlock) void k_f32_to_bf16(const float *__restrict__ in,
+                                                        uint16_t *__restrict__ out, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        out[i] = f32_to_bf16_rne(in[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_triad(float4 *__restrict__ a,
+                                                  const float4 *__restrict__ b,
+                                                  const float4 *__restrict__ c, float s,
+                                                  int64_t nq) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nq; i += stride) {
+        float4 x = b[i], y = c[i];
+        a[i] = make_float4(x.x + s * y.x, x.y + s * y.y, x.z + s * y.z, x.w + s * y.w);
+    }
+}
+
+__global__ void k_triad_tail(float *a, const float *b, const float *c, float s, int64_t lo,
+                             int64_t n) {
+    int64_t i = lo + threadIdx.x;
+    if (i < n) a[i] = b[i] + s * c[i];
+}
+
+}  // namespace spt
+
+using namespace spt;
+
+extern "C" int spt_f32_to_bf16(const float *in, uint16_t *out, int64_t n, void *stream) {
+    if (n < 0 || (n > 0 && (in == nullptr || out == nullptr))) return SPT_EINVAL;
+    if (n == 0) return SPT_OK;
+    int64_t blocks = ceil_div(n, kBlock);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)blocks), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), in, out, n);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+extern "C" int spt_stream_triad(float *a, const float *b, const float *c, float s, int64_t n,
+                                void *stream) {
+    if (n < 0 || (n > 0 && (a == nullptr || b == nullptr || c == nullptr))) return SPT_EINVAL;
+    if ((((uintptr_t)a) | ((uintptr_t)b) | ((uintptr_t)c)) & 15u) return SPT_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t nq = n / 4;
+    if (nq > 0) {
+        int64_t blocks = ceil_div(nq, kBlock);
+        if (blocks > 256 * 32) blocks = 256 * 32;
+        hipLaunchKernelGGL(k_triad, dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                           reinterpret_cast<float4 *>(a), reinterpret_cast<const float4 *>(b),
+                           reinterpret_cast<const float4 *>(c), s, nq);
+    }
+    if (nq * 4 < n)
+        hipLaunchKernelGGL(k_triad_tail, dim3(1), dim3(64), 0, st, a, b, c, s, nq * 4, n);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}

@@ -1,0 +1,163 @@
+// Public MTTKRP entry point: argument checks, launch-parameter choice, output zeroing and
+// dispatch to the per-dtype kernel instantiations.
+#include "mttkrp_kernels.h"
+
+namespace spt {
+
+// Zero n bytes (n a multiple of 4) with a kernel rather than a memset node, so the call can be
+// captured in a HIP graph.
+__global__ __launch_bounds__(kBlock) void k_zero(uint32_t *__restrict__ p, int64_t nwords) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t nq = nwords / 4;
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+    for (int64_t k = i; k < nq; k += stride) q[k] = make_uint4(0, 0, 0, 0);
+    for (int64_t k = nq * 4 + i; k < nwords; k += stride) p[k] = 0;
+}
+
+int zero_words(void *p, int64_t nwords, hipStream_t s) {
+    if (nwords <= 0) return SPT_OK;
+    int64_t blocks = ceil_div(ceil_div(nwords, 4), kBlock);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       static_cast<uint32_t *>(p), nwords);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+static bool cfg_supported(int G, int CPL) {
+    switch (G * 8 + CPL) {
+        case 8 * 8 + 1: case 16 * 8 + 1: case 32 * 8 + 1: case 64 * 8 + 1:
+        case 8 * 8 + 2: case 16 * 8 + 2: case 32 * 8 + 2: case 64 * 8 + 2:
+        case 16 * 8 + 4: case 64 * 8 + 4:
+            return true;
+        default:
+            return false;
+    }
+}
+
+static int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static int default_hbits(int R, int G, int CPL, int fdtype, int rq) {
+    // LDS budget for the hash table: 48 KiB minus the record staging buffer
+    const int at = (fdtype == SPT_F64) ? 8 : 4;
+    const int budget = 48 * 1024 - (kBlock / kWave) * kWave * rq * 16;
+    const int per_slot = G * CPL * at + 4;
+    int hb = 0;
+    while (hb < 12 && (2 << hb) * per_slot <= budget) ++hb;
+    (void)R;
+    return hb;
+}
+
+int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tune *in,
+                 spt_tune *out) {
+    spt_tune t = in ? *in : spt_tune{0, 0, 0, 0};
+    if (t.algo == SPT_ALGO_AUTO) t.algo = X->permuted[mode] ? SPT_ALGO_PERMUTED : SPT_ALGO_ATOMIC;
+    if (t.algo != SPT_ALGO_ATOMIC && t.algo != SPT_ALGO_PERMUTED) return SPT_EINVAL;
+    int cpl = t.cols_per_lane;
+    if (cpl == 0) {
+        if (fdtype == SPT_BF16 && R % 2 == 0 && R <= 128) cpl = 2;
+        else if (R <= 64) cpl = 1;
+        else if (R <= 128) cpl = 2;
+        else cpl = 4;
+        if (cpl == 4 && R % 4 != 0) cpl = 2;
+        if (cpl == 2 && R % 2 != 0) cpl = 1;
+    }
+    if (cpl != 1 && cpl != 2 && cpl != 4) return SPT_EINVAL;
+    if (R % cpl != 0) return SPT_EUNSUPPORTED;
+    int G = t.lanes_per_nnz;
+    if (G == 0) {
+        G = pow2_at_least((R + cpl - 1) / cpl);
+        if (G < 8) G = 8;
+        if (cpl == 4 && G < 64 && G > 16) G = 64;
+        if (cpl == 4 && G < 16) G = 16;
+    }
+    if (G * cpl < R || !cfg_supported(G, cpl)) return SPT_EUNSUPPORTED;
+    if (t.nnz_per_wave == 0) t.nnz_per_wave = 2048;
+    if (t.nnz_per_wave < 64 || t.nnz_per_wave % 64 != 0 || t.nnz_per_wave > (1 << 20))
+        return SPT_EINVAL;
+    t.lanes_per_nnz = G;
+    t.cols_per_lane = cpl;
+    *out = t;
+    return SPT_OK;
+}
+
+int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *factors, int fdtype,
+                  const double *lambda, const void *vals, void *V, const spt_tune &t,
+                  hipStream_t s) {
+    const int at_bytes = (fdtype == SPT_F64) ? 8 : 4;
+    int rc = zero_words(V, X->dims[mode] * (int64_t)R * at_bytes / 4, s);
+    if (rc) return rc;
+    if (X->P == 0) return SPT_OK;
+    MttkrpArgs a;
+    a.rec = X->rec;
+    a.perm = X->perm[mode];
+    a.P = X->P;
+    a.n = mode;
+    a.R = R;
+    a.lambda = lambda;
+    a.vovr = vals;
+    a.V = V;
+    a.chunk = t.nnz_per_wave;
+    a.algo = t.algo;
+    a.hbits = default_hbits(R, t.lanes_per_nnz, t.cols_per_lane, fdtype, X->rec_words / 4);
+    a.stream = s;
+    switch (fdtype) {
+        case SPT_F64: return launch_mttkrp_f64(a, X->d, factors, t.lanes_per_nnz, t.cols_per_lane);
+        case SPT_F32: return launch_mttkrp_f32(a, X->d, factors, t.lanes_per_nnz, t.cols_per_lane);
+        case SPT_BF16:
+            return launch_mttkrp_bf16(a, X->d, factors, t.lanes_per_nnz, t.cols_per_lane);
+        default: return SPT_EINVAL;
+    }
+}
+
+static int check_dtypes(const spt_tensor *X, int fdtype) {
+    if (fdtype == SPT_F64) return X->vdtype == SPT_F64 ? SPT_OK : SPT_EUNSUPPORTED;
+    if (fdtype == SPT_F32 || fdtype == SPT_BF16)
+        return X->vdtype == SPT_F32 ? SPT_OK : SPT_EUNSUPPORTED;
+    return SPT_EINVAL;
+}
+
+int check_factors(const spt_tensor *X, int skip_mode, const void *const *factors) {
+    if (factors == nullptr) return SPT_EINVAL;
+    for (int m = 0; m < X->d; ++m)
+        if (m != skip_mode && factors[m] == nullptr) return SPT_EINVAL;
+    return SPT_OK;
+}
+
+int check_mttkrp_args(const spt_tensor *X, int mode, int R, const void *const *factors,
+                      int fdtype, const void *V) {
+    if (X == nullptr || mode < 0 || mode >= X->d || R < 1 || R > 256 || V == nullptr)
+        return SPT_EINVAL;
+    int rc = check_factors(X, mode, factors);
+    if (rc) return rc;
+    return check_dtypes(X, fdtype);
+}
+
+}  // namespace spt
+
+using namespace spt;
+
+extern "C" int spt_mttkrp(const spt_tensor *X, int mode, int R, const void *const *factors,
+                          int fdtype, const double *lambda, const void *vals, void *V,
+                          const spt_tune *tune, void *stream) {
+    int rc = check_mttkrp_args(X, mode, R, factors, fdtype, V);
+    if (rc) return rc;
+    spt_tune t;
+    rc = resolve_tune(X, mode, R, fdtype, tune, &t);
+    if (rc) return rc;
+    if (t.algo == SPT_ALGO_PERMUTED && !X->permuted[mode]) return SPT_ESTATE;
+    return launch_mttkrp(X, mode, R, factors, fdtype, lambda, vals, V, t,
+                         static_cast<hipStream_t>(stream));
+}
+
+extern "C" int spt_mttkrp_default_tune(const spt_tensor *X, int mode, int R, int fdtype,
+                                       int algo, spt_tune *out) {
+    if (X == nullptr || out == nullptr || mode < 0 || mode >= X->d || R < 1 || R > 256)
+        return SPT_EINVAL;
+    spt_tune in{algo, 0, 0, 0};
+    return resolve_tune(X, mode, R, fdtype, &in, out);
+}

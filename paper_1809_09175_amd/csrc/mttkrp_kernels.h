@@ -1,0 +1,465 @@
+// MTTKRP kernels (eq. (mttkrp), Sec. 3) for gfx950, included by the per-dtype translation units.
+//
+// Work mapping shared by both kernels (the paper's league/team/vector hierarchy, Sec. 4.1,
+// re-cast for 64-wide wavefronts):
+//   - a wavefront owns a contiguous chunk of entries (storage order or mode-n sorted order);
+//   - the wave is split into NG = 64/G lane groups; a group handles one entry at a time and its
+//     G lanes hold CPL consecutive rank columns each (the register-resident row slice that the
+//     paper's compile-time polymorphic arrays provide, Sec. 4.3);
+//   - 64 entry records are fetched per batch with one 16/32-byte load per lane and staged in
+//     LDS, from where each group reads its entry with one broadcast LDS load;
+//   - U entries are gathered ahead (all factor-row loads issued before any is consumed) so
+//     several row gathers are in flight per lane.
+//
+// k_mttkrp_perm walks the mode-n sorted order (Sec. 5).  Each group owns a contiguous slice of
+// the wave's chunk and keeps a running row sum while the mode-n subscript is unchanged; a row
+// that starts and ends inside the slice is written with a plain store.  The first and last
+// rows of each slice meet in LDS, where the wave combines them (a segmented reduction across
+// its groups); only the chunk's first and last rows, which neighbouring waves may share, are
+// added atomically.  No LDS table and no barrier beyond the wavefront.
+//
+// k_mttkrp_atomic walks storage order.  Each product row is added into a per-workgroup LDS
+// hash table keyed by output row (claimed with LDS compare-and-swap, short linear probe); rows
+// that find no slot go straight to global atomics.  At the end the workgroup adds every table
+// row to V with one global atomic per column.  This stages partial sums in LDS so a hot output
+// row receives one global atomic per workgroup instead of one per entry.
+#pragma once
+
+#include "spt_internal.h"
+
+namespace spt {
+
+template <int D, class VT>
+struct RecShape {
+    static constexpr int RW = (D * 4 + (int)sizeof(VT) <= 16) ? 4 : 8;  // 32-bit words
+    static constexpr int RQ = RW / 4;                                     // 16-byte quads
+};
+
+template <class VT, int RW>
+__device__ __forceinline__ VT rec_value(const int *w) {
+    if constexpr (sizeof(VT) == 8)
+        return __hiloint2double(w[RW - 1], w[RW - 2]);
+    else
+        return __int_as_float(w[RW - 1]);
+}
+
+template <class VT, int RW>
+__device__ __forceinline__ void rec_set_value(int *w, VT v) {
+    if constexpr (sizeof(VT) == 8) {
+        w[RW - 2] = __double2loint(v);
+        w[RW - 1] = __double2hiint(v);
+    } else {
+        w[RW - 1] = __float_as_int(v);
+    }
+}
+
+template <int D, int RW>
+__device__ __forceinline__ int rec_sub(const int *w, int n) {
+    int k = w[0];
+#pragma unroll
+    for (int m = 1; m < D; ++m) k = (m == n) ? w[m] : k;
+    return k;
+}
+
+// CPL consecutive factor entries, widened to the accumulation type
+template <class FT, int CPL, class AT>
+__device__ __forceinline__ void load_cols(const FT *__restrict__ p, AT *out) {
+    if constexpr (sizeof(FT) == 2) {  // BF16 bit patterns
+        if constexpr (CPL == 1) {
+            out[0] = bf16_bits_to_f32(*reinterpret_cast<const uint16_t *>(p));
+        } else if constexpr (CPL == 2) {
+            uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+            out[0] = bf16_bits_to_f32(v & 0xffffu);
+            out[1] = bf16_bits_to_f32(v >> 16);
+        } else {
+            uint2 v = *reinterpret_cast<const uint2 *>(p);
+            out[0] = bf16_bits_to_f32(v.x & 0xffffu);
+            out[1] = bf16_bits_to_f32(v.x >> 16);
+            out[2] = bf16_bits_to_f32(v.y & 0xffffu);
+            out[3] = bf16_bits_to_f32(v.y >> 16);
+        }
+    } else if constexpr (sizeof(FT) == 4) {
+        if constexpr (CPL == 1) {
+            out[0] = *p;
+        } else if constexpr (CPL == 2) {
+            float2 v = *reinterpret_cast<const float2 *>(p);
+            out[0] = v.x;
+            out[1] = v.y;
+        } else {
+            float4 v = *reinterpret_cast<const float4 *>(p);
+            out[0] = v.x;
+            out[1] = v.y;
+            out[2] = v.z;
+            out[3] = v.w;
+        }
+    } else {
+        if constexpr (CPL == 1) {
+            out[0] = *p;
+        } else {
+#pragma unroll
+            for (int h = 0; h < CPL; h += 2) {
+                double2 v = *reinterpret_cast<const double2 *>(p + h);
+                out[h] = v.x;
+                out[h + 1] = v.y;
+            }
+        }
+    }
+}
+
+template <class AT, int CPL>
+__device__ __forceinline__ void store_cols(AT *__restrict__ p, const AT *v) {
+    if constexpr (sizeof(AT) == 4 && CPL == 2) {
+        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+    } else if constexpr (sizeof(AT) == 4 && CPL == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) p[c] = v[c];
+    }
+}
+
+template <class AT, int CPL>
+__device__ __forceinline__ void atomic_cols(AT *__restrict__ p, const AT *v) {
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) atomic_add_f(p + c, v[c]);
+}
+
+// Product row of one entry: t[c] = x * lambda_j * prod_{m != n} A^(m)(l_m, j), for this lane's
+// columns j = col0 .. col0+CPL-1 (multiply order as in Sec. 4.1: x times the weight first,
+// then each other mode in increasing order).
+template <int D, int RW, int CPL, class FT, class VT, class AT>
+__device__ __forceinline__ void entry_product(const int *w, int n, int R, int col0, bool colok,
+                                              const FactorSet<FT> &A, const AT *lam, AT *t) {
+    const AT x = (AT)rec_value<VT, RW>(w);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) t[c] = x * lam[c];
+    if (colok) {
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            if (m != n) {
+                AT f[CPL];
+                load_cols<FT, CPL, AT>(A.p[m] + (int64_t)w[m] * R + col0, f);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) t[c] *= f[c];
+            }
+        }
+    }
+}
+
+template <int D, int G, int CPL, class FT, class VT, class AT>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
+    const int4 *__restrict__ rec, const int32_t *__restrict__ perm, int64_t P, int n, int R,
+    FactorSet<FT> A, const double *__restrict__ lambda, const VT *__restrict__ vovr,
+    AT *__restrict__ V, int chunk) {
+    constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
+    constexpr int NG = kWave / G;
+    constexpr int U = (CPL >= 4) ? 4 : 8;
+    __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
+    __shared__ AT s_part[kBlock / kWave][2 * NG][G * CPL];
+    __shared__ int s_pkey[kBlock / kWave][2 * NG];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane / G, gl = lane % G;
+    const int col0 = gl * CPL;
+    const bool colok = col0 < R;
+    const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
+    if (c0 >= P) return;  // whole wavefront leaves together
+    const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
+    const int S = chunk / NG;  // slice per group
+    const int64_t gb = c0 + (int64_t)g * S;
+    const int64_t ge = (gb + S < c1) ? gb + S : c1;
+    const int glen = ge > gb ? (int)(ge - gb) : 0;
+    const int wlen = (int)((c1 - c0) < S ? (c1 - c0) : S);
+    const int nb = (wlen + G - 1) / G;
+
+    AT lam[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+        lam[c] = (lambda != nullptr && colok) ? (AT)lambda[col0 + c] : (AT)1;
+    if (gl == 0) {
+        s_pkey[wave][2 * g] = -1;
+        s_pkey[wave][2 * g + 1] = -1;
+    }
+
+    int key = -1, first_key = -1;
+    AT acc[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] = 0;
+
+    for (int b = 0; b < nb; ++b) {
+        const int off = b * G + gl;
+        if (off < glen) {
+            const int p = perm[gb + off];
+            const int4 *r = rec + (int64_t)p * RQ;
+            s_rec[wave][lane * RQ] = r[0];
+            if constexpr (RQ == 2) s_rec[wave][lane * RQ + 1] = r[1];
+            if (vovr != nullptr)
+                rec_set_value<VT, RW>(reinterpret_cast<int *>(&s_rec[wave][lane * RQ]), vovr[p]);
+        }
+        wave_sync();
+        const int cnt = glen - b * G < G ? glen - b * G : G;
+        for (int s0 = 0; s0 < cnt; s0 += U) {
+            AT t[U][CPL];
+            int kk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int s = s0 + u;
+                kk[u] = -1;
+                if (s < cnt) {
+                    int w[RW];
+                    const int4 *q = &s_rec[wave][(g * G + s) * RQ];
+                    int4 a = q[0];
+                    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+                    if constexpr (RQ == 2) {
+                        int4 bq = q[1];
+                        w[4] = bq.x; w[5] = bq.y; w[6] = bq.z; w[7] = bq.w;
+                    }
+                    kk[u] = rec_sub<D, RW>(w, n);
+                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, R, col0, colok, A, lam, t[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (kk[u] >= 0) {
+                    if (kk[u] != key) {
+                        if (key >= 0) {
+                            if (key == first_key) {
+#pragma unroll
+                                for (int c = 0; c < CPL; ++c) s_part[wave][2 * g][col0 + c] = acc[c];
+                                if (gl == 0) s_pkey[wave][2 * g] = key;
+                            } else if (colok) {
+                                store_cols<AT, CPL>(V + (int64_t)key * R + col0, acc);
+                            }
+                        } else {
+                            first_key = kk[u];
+                        }
+                        key = kk[u];
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) acc[c] = 0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) acc[c] += t[u][c];
+                }
+            }
+        }
+        wave_sync();
+    }
+    if (key >= 0) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) s_part[wave][2 * g + 1][col0 + c] = acc[c];
+        if (gl == 0) s_pkey[wave][2 * g + 1] = key;
+    }
+    wave_sync();
+    if (g == 0) {
+        int ck = -1;
+        bool first_seg = true;
+        AT cacc[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cacc[c] = 0;
+        for (int e = 0; e < 2 * NG; ++e) {
+            const int ke = s_pkey[wave][e];
+            if (ke < 0) continue;
+            if (ke != ck) {
+                if (ck >= 0 && colok) {
+                    if (first_seg) atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+                    else store_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+                }
+                if (ck >= 0) first_seg = false;
+                ck = ke;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) cacc[c] = 0;
+            }
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) cacc[c] += s_part[wave][e][col0 + c];
+        }
+        if (ck >= 0 && colok) atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+    }
+}
+
+template <int D, int G, int CPL, class FT, class VT, class AT>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
+    const int4 *__restrict__ rec, int64_t P, int n, int R, FactorSet<FT> A,
+    const double *__restrict__ lambda, const VT *__restrict__ vovr, AT *__restrict__ V,
+    int chunk, int hbits) {
+    constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
+    constexpr int NG = kWave / G;
+    constexpr int RP = G * CPL;
+    constexpr int U = (CPL >= 4) ? 4 : 8;
+    extern __shared__ int4 smem4[];
+    int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
+    int *hkeys = reinterpret_cast<int *>(smem4 + (kBlock / kWave) * kWave * RQ);
+    const int H = hbits > 0 ? (1 << hbits) : 0;
+    AT *hvals = reinterpret_cast<AT *>(hkeys + (H > 2 ? H : 2));
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane / G, gl = lane % G;
+    const int col0 = gl * CPL;
+    const bool colok = col0 < R;
+    for (int i = tid; i < H; i += kBlock) hkeys[i] = -1;
+    for (int i = tid; i < H * RP; i += kBlock) hvals[i] = 0;
+    __syncthreads();
+
+    AT lam[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+        lam[c] = (lambda != nullptr && colok) ? (AT)lambda[col0 + c] : (AT)1;
+
+    const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
+    const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
+    const int len = c1 > c0 ? (int)(c1 - c0) : 0;
+    const int nb = (len + kWave - 1) / kWave;
+    for (int b = 0; b < nb; ++b) {
+        const int off = b * kWave + lane;
+        if (off < len) {
+            const int4 *r = rec + (c0 + off) * RQ;
+            s_rec[lane * RQ] = r[0];
+            if constexpr (RQ == 2) s_rec[lane * RQ + 1] = r[1];
+            if (vovr != nullptr)
+                rec_set_value<VT, RW>(reinterpret_cast<int *>(&s_rec[lane * RQ]), vovr[c0 + off]);
+        }
+        wave_sync();
+        int cnt = len - b * kWave - g * G;
+        cnt = cnt < G ? cnt : G;
+        for (int s0 = 0; s0 < cnt; s0 += U) {
+            AT t[U][CPL];
+            int kk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int s = s0 + u;
+                kk[u] = -1;
+                if (s < cnt) {
+                    int w[RW];
+                    const int4 *q = &s_rec[(g * G + s) * RQ];
+                    int4 a = q[0];
+                    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+                    if constexpr (RQ == 2) {
+                        int4 bq = q[1];
+                        w[4] = bq.x; w[5] = bq.y; w[6] = bq.z; w[7] = bq.w;
+                    }
+                    kk[u] = rec_sub<D, RW>(w, n);
+                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, R, col0, colok, A, lam, t[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = kk[u];
+                if (k < 0) continue;
+                int slot = -1;
+                if (H > 0) {
+                    uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - hbits);
+                    for (int probe = 0; probe < 4; ++probe) {
+                        int cur = __hip_atomic_load(&hkeys[h], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (cur == k) {
+                            slot = (int)h;
+                            break;
+                        }
+                        if (cur == -1) {
+                            int old = atomicCAS(&hkeys[h], -1, k);
+                            if (old == -1 || old == k) {
+                                slot = (int)h;
+                                break;
+                            }
+                        }
+                        h = (h + 1) & (uint32_t)(H - 1);
+                    }
+                }
+                if (colok) {
+                    if (slot >= 0) {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) atomicAdd(&hvals[slot * RP + col0 + c], t[u][c]);
+                    } else {
+                        atomic_cols<AT, CPL>(V + (int64_t)k * R + col0, t[u]);
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+    __syncthreads();
+    for (int i = tid; i < H * RP; i += kBlock) {
+        const int slot = i / RP, col = i - slot * RP;
+        const int k = hkeys[slot];
+        if (k >= 0 && col < R) atomic_add_f(V + (int64_t)k * R + col, hvals[i]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// launch dispatch over (order, lane config) for one dtype triple
+// ------------------------------------------------------------------------------------------
+
+struct MttkrpArgs {
+    const int4 *rec;
+    const int32_t *perm;
+    int64_t P;
+    int n, R;
+    const double *lambda;
+    const void *vovr;
+    void *V;
+    int chunk;
+    int hbits;
+    int algo;
+    hipStream_t stream;
+};
+
+template <class AT>
+inline size_t atomic_smem_bytes(int RQ, int H, int RP) {
+    return (size_t)(kBlock / kWave) * kWave * RQ * 16 + (size_t)(H > 2 ? H : 2) * 4 +
+           (size_t)H * RP * sizeof(AT);
+}
+
+template <int D, int G, int CPL, class FT, class VT, class AT>
+int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
+    const VT *vovr = static_cast<const VT *>(a.vovr);
+    AT *V = static_cast<AT *>(a.V);
+    const int64_t per_block = (int64_t)a.chunk * (kBlock / kWave);
+    const unsigned grid = (unsigned)ceil_div(a.P, per_block);
+    if (grid == 0) return SPT_OK;
+    if (a.algo == SPT_ALGO_PERMUTED) {
+        hipLaunchKernelGGL((k_mttkrp_perm<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock), 0,
+                           a.stream, a.rec, a.perm, a.P, a.n, a.R, A, a.lambda, vovr, V, a.chunk);
+    } else {
+        const int H = a.hbits > 0 ? (1 << a.hbits) : 0;
+        const size_t smem = atomic_smem_bytes<AT>(RecShape<D, VT>::RQ, H, G * CPL);
+        hipLaunchKernelGGL((k_mttkrp_atomic<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock),
+                           smem, a.stream, a.rec, a.P, a.n, a.R, A, a.lambda, vovr, V, a.chunk,
+                           a.hbits);
+    }
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+template <int D, class FT, class VT, class AT>
+int launch_d(const MttkrpArgs &a, const FactorSet<FT> &A, int G, int CPL) {
+    switch (G * 8 + CPL) {
+        case 8 * 8 + 1: return launch_cfg<D, 8, 1, FT, VT, AT>(a, A);
+        case 16 * 8 + 1: return launch_cfg<D, 16, 1, FT, VT, AT>(a, A);
+        case 32 * 8 + 1: return launch_cfg<D, 32, 1, FT, VT, AT>(a, A);
+        case 64 * 8 + 1: return launch_cfg<D, 64, 1, FT, VT, AT>(a, A);
+        case 8 * 8 + 2: return launch_cfg<D, 8, 2, FT, VT, AT>(a, A);
+        case 16 * 8 + 2: return launch_cfg<D, 16, 2, FT, VT, AT>(a, A);
+        case 32 * 8 + 2: return launch_cfg<D, 32, 2, FT, VT, AT>(a, A);
+        case 64 * 8 + 2: return launch_cfg<D, 64, 2, FT, VT, AT>(a, A);
+        case 16 * 8 + 4: return launch_cfg<D, 16, 4, FT, VT, AT>(a, A);
+        case 64 * 8 + 4: return launch_cfg<D, 64, 4, FT, VT, AT>(a, A);
+        default: return SPT_EUNSUPPORTED;
+    }
+}
+
+template <class FT, class VT, class AT>
+int launch_typed(const MttkrpArgs &a, int d, const void *const *factors, int G, int CPL) {
+    FactorSet<FT> A{};
+    for (int m = 0; m < d; ++m) A.p[m] = static_cast<const FT *>(factors[m]);
+    switch (d) {
+        case 2: return launch_d<2, FT, VT, AT>(a, A, G, CPL);
+        case 3: return launch_d<3, FT, VT, AT>(a, A, G, CPL);
+        case 4: return launch_d<4, FT, VT, AT>(a, A, G, CPL);
+        case 5: return launch_d<5, FT, VT, AT>(a, A, G, CPL);
+        default: return SPT_EUNSUPPORTED;
+    }
+}
+
+int launch_mttkrp_f64(const MttkrpArgs &a, int d, const void *const *factors, int G, int CPL);
+int launch_mttkrp_f32(const MttkrpArgs &a, int d, const void *const *factors, int G, int CPL);
+int launch_mttkrp_bf16(const MttkrpArgs &a, int d, const void *const *factors, int G, int CPL);
+
+}  // namespace spt

@@ -1,0 +1,496 @@
+// COO tensor storage for libspt: packing of the caller's subscripts and values into records,
+// and the per-mode permutations of Sec. 5 built by a stable LSD radix sort (8-bit digits,
+// reduce-then-scan, LDS ranking with wavefront ballots).
+#include <string.h>
+
+#include <new>
+
+#include "spt_internal.h"
+
+namespace spt {
+
+// ------------------------------------------------------------------------------------------
+// packing: P x d int32 subscripts + values -> records {l_0 .. l_{d-1}, pad, value}
+// ------------------------------------------------------------------------------------------
+
+template <class VT, int RW>
+__global__ __launch_bounds__(kBlock) void k_pack(const int32_t *__restrict__ subs,
+                                                  const VT *__restrict__ vals, int d, int64_t P,
+                                                  int4 *__restrict__ rec, SptStatusBlock *st,
+                                                  int64_t dim0, int64_t dim1, int64_t dim2,
+                                                  int64_t dim3, int64_t dim4) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= P) return;
+    const int64_t dims[SPT_MAX_ORDER] = {dim0, dim1, dim2, dim3, dim4};
+    int32_t w[RW];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) w[k] = 0;
+    bool bad = false;
+#pragma unroll
+    for (int m = 0; m < SPT_MAX_ORDER; ++m) {
+        if (m < d) {
+            int32_t l = subs[i * d + m];
+            if (l < 0 || (int64_t)l >= dims[m]) {
+                bad = true;
+                l = 0;  // keep every later access in bounds
+            }
+            w[m] = l;
+        }
+    }
+    VT v = vals[i];
+    if constexpr (sizeof(VT) == 8) {
+        uint64_t b = __double_as_longlong(v);
+        w[RW - 2] = (int32_t)(uint32_t)b;
+        w[RW - 1] = (int32_t)(uint32_t)(b >> 32);
+    } else {
+        w[RW - 1] = __float_as_int(v);
+    }
+    int4 *out = rec + i * (RW / 4);
+    out[0] = make_int4(w[0], w[1], w[2], w[3]);
+    if constexpr (RW == 8) out[1] = make_int4(w[4], w[5], w[6], w[7]);
+    if (bad) {
+        raise_status(st, SPT_ERANGE);
+        atomicMin((unsigned long long *)&st->bad_entry, (unsigned long long)i);
+    }
+}
+
+__global__ void k_status_init(SptStatusBlock *st) {
+    st->code = 0;
+    st->pad = 0;
+    st->bad_entry = INT64_MAX;
+}
+
+// ------------------------------------------------------------------------------------------
+// radix sort: keys are mode-n subscripts (non-negative int32), values are entry positions
+// ------------------------------------------------------------------------------------------
+
+// Reads the pass input key of element e: from the records on the first pass, else from keys.
+template <bool FIRST>
+__device__ __forceinline__ int32_t sort_key(const int32_t *keys, const int32_t *recw, int rw,
+                                            int n, int64_t e) {
+    if constexpr (FIRST) return recw[e * rw + n];
+    else return keys[e];
+}
+
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *__restrict__ keys,
+                                                        const int32_t *__restrict__ recw, int rw,
+                                                        int n, int64_t P, int shift,
+                                                        uint32_t *__restrict__ counts,
+                                                        int64_t ntiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t e = base + it * kBlock + threadIdx.x;
+        if (e < P) {
+            uint32_t dg = ((uint32_t)sort_key<FIRST>(keys, recw, rw, n, e) >> shift) & 255u;
+            atomicAdd(&h[dg], 1u);
+        }
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// block-wide exclusive scan of one value per thread; returns the block total in *total
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        if (w < wave) before += wsum[w];
+        all += wsum[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ a, int64_t L,
+                                                         uint32_t *__restrict__ part) {
+    int64_t base = (int64_t)blockIdx.x * kScanSeg + threadIdx.x * 8;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (base + k < L) s += a[base + k];
+    uint32_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t *part, int64_t nb) {
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        int64_t b = b0 + threadIdx.x;
+        uint32_t v = b < nb ? part[b] : 0;
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(v, &tot);
+        if (b < nb) part[b] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t *__restrict__ a, int64_t L,
+                                                       const uint32_t *__restrict__ part) {
+    int64_t base = (int64_t)blockIdx.x * kScanSeg + threadIdx.x * 8;
+    uint32_t v[8];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = (base + k < L) ? a[base + k] : 0;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (base + k < L) a[base + k] = run;
+        run += v[k];
+    }
+}
+
+// Stable scatter of one tile: element order inside the tile is (item, wave, lane).
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const int32_t *__restrict__ keys, const int32_t *__restrict__ vals,
+    const int32_t *__restrict__ recw, int rw, int n, int64_t P, int shift,
+    const uint32_t *__restrict__ offsets, int64_t ntiles, int32_t *__restrict__ okeys,
+    int32_t *__restrict__ ovals) {
+    __shared__ uint16_t cnt[kSortItems][kBlock / kWave][256];
+    __shared__ uint32_t gofs[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    {
+        uint32_t *c32 = reinterpret_cast<uint32_t *>(&cnt[0][0][0]);
+        for (int k = tid; k < kSortItems * (kBlock / kWave) * 128; k += kBlock) c32[k] = 0;
+        gofs[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x];
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    int32_t k_[kSortItems], v_[kSortItems];
+    uint32_t dg_[kSortItems];
+    uint16_t rk_[kSortItems];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t e = base + it * kBlock + tid;
+        bool valid = e < P;
+        int32_t key = valid ? sort_key<FIRST>(keys, recw, rw, n, e) : 0;
+        int32_t val = 0;
+        if (valid) val = FIRST ? (int32_t)e : vals[e];
+        uint32_t dg = ((uint32_t)key >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (dg >> b) & 1u;
+            uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        rk_[it] = (uint16_t)__popcll(m & lt);
+        if (valid && (__ffsll((unsigned long long)m) - 1) == lane)
+            cnt[it][wave][dg] = (uint16_t)__popcll(m);
+        k_[it] = key;
+        v_[it] = val;
+        dg_[it] = valid ? dg : 256u;
+    }
+    __syncthreads();
+    {   // per digit: exclusive prefix over (item, wave) in element order
+        uint32_t run = 0;
+        for (int it = 0; it < kSortItems; ++it)
+            for (int w = 0; w < kBlock / kWave; ++w) {
+                uint32_t c = cnt[it][w][tid];
+                cnt[it][w][tid] = (uint16_t)run;
+                run += c;
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        uint32_t dg = dg_[it];
+        if (dg < 256u) {
+            uint32_t dst = gofs[dg] + cnt[it][wave][dg] + rk_[it];
+            okeys[dst] = k_[it];
+            ovals[dst] = v_[it];
+        }
+    }
+}
+
+__global__ void k_iota_perm(int32_t *perm, int32_t *skey, int64_t P) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < P) {
+        perm[i] = (int32_t)i;
+        skey[i] = 0;
+    }
+}
+
+static int bit_width(int64_t x) {  // bits needed for values 0..x
+    int b = 0;
+    while (x > 0) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+static int permute_mode(spt_tensor *X, int n, hipStream_t s) {
+    const int64_t P = X->P;
+    if (P == 0) {
+        X->permuted[n] = 1;
+        return SPT_OK;
+    }
+    const int nbits = bit_width(X->dims[n] - 1);
+    if (nbits == 0) {
+        hipLaunchKernelGGL(k_iota_perm, dim3((unsigned)ceil_div(P, kBlock)), dim3(kBlock), 0, s,
+                           X->perm[n], X->skey[n], P);
+        SPT_LAUNCH_CHECK();
+        X->permuted[n] = 1;
+        return SPT_OK;
+    }
+    const int passes = (nbits + 7) / 8;
+    const int64_t ntiles = ceil_div(P, kSortTile);
+    const int64_t L = 256 * ntiles;
+    const int64_t nseg = ceil_div(L, kScanSeg);
+    const int32_t *recw = reinterpret_cast<const int32_t *>(X->rec);
+    const int32_t *ik = nullptr, *iv = nullptr;
+    for (int pass = 0; pass < passes; ++pass) {
+        const bool to_final = ((passes - 1 - pass) % 2) == 0;
+        int32_t *ok = to_final ? X->skey[n] : X->tmp_keys;
+        int32_t *ov = to_final ? X->perm[n] : X->tmp_vals;
+        const int shift = pass * 8;
+        dim3 g((unsigned)ntiles), b(kBlock);
+        if (pass == 0)
+            hipLaunchKernelGGL(k_radix_hist<true>, g, b, 0, s, ik, recw, X->rec_words, n, P,
+                               shift, X->hist, ntiles);
+        else
+            hipLaunchKernelGGL(k_radix_hist<false>, g, b, 0, s, ik, recw, X->rec_words, n, P,
+                               shift, X->hist, ntiles);
+        SPT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nseg), b, 0, s, X->hist, L,
+                           X->scan_part);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), b, 0, s, X->scan_part, nseg);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nseg), b, 0, s, X->hist, L, X->scan_part);
+        SPT_LAUNCH_CHECK();
+        if (pass == 0)
+            hipLaunchKernelGGL(k_radix_scatter<true>, g, b, 0, s, ik, iv, recw, X->rec_words, n,
+                               P, shift, X->hist, ntiles, ok, ov);
+        else
+            hipLaunchKernelGGL(k_radix_scatter<false>, g, b, 0, s, ik, iv, recw, X->rec_words,
+                               n, P, shift, X->hist, ntiles, ok, ov);
+        SPT_LAUNCH_CHECK();
+        ik = ok;
+        iv = ov;
+    }
+    X->permuted[n] = 1;
+    return SPT_OK;
+}
+
+// workspace layout -----------------------------------------------------------------------------
+
+struct WsLayout {
+    size_t status, rec, perm, skey, tmp_keys, tmp_vals, hist, scan_part, red, total;
+};
+
+static bool layout(int d, const int64_t *dims, int64_t P, int vdtype, WsLayout *L) {
+    if (d < 2 || d > SPT_MAX_ORDER || dims == nullptr || P < 0 || P > INT32_MAX) return false;
+    if (vdtype != SPT_F64 && vdtype != SPT_F32) return false;
+    for (int m = 0; m < d; ++m)
+        if (dims[m] < 1 || dims[m] > INT32_MAX) return false;
+    const int rw = rec_words_for(d, vdtype);
+    const int64_t ntiles = ceil_div(P, kSortTile);
+    const int64_t Lh = 256 * (ntiles > 0 ? ntiles : 1);
+    size_t o = 0;
+    L->status = o;
+    o += align256(sizeof(SptStatusBlock));
+    L->rec = o;
+    o += align256((size_t)P * rw * 4);
+    L->perm = o;
+    o += (size_t)d * align256((size_t)P * 4);
+    L->skey = o;
+    o += (size_t)d * align256((size_t)P * 4);
+    L->tmp_keys = o;
+    o += align256((size_t)P * 4);
+    L->tmp_vals = o;
+    o += align256((size_t)P * 4);
+    L->hist = o;
+    o += align256((size_t)Lh * 4);
+    L->scan_part = o;
+    o += align256((size_t)(ceil_div(Lh, kScanSeg) + 1) * 4);
+    L->red = o;
+    o += align256((size_t)kRedSlots * 8);
+    L->total = o;
+    return true;
+}
+
+}  // namespace spt
+
+using namespace spt;
+
+extern "C" {
+
+const char *spt_status_string(int status) {
+    switch (status) {
+        case SPT_OK: return "ok";
+        case SPT_EINVAL: return "invalid argument";
+        case SPT_ERANGE: return "subscript out of range";
+        case SPT_EHIP: return "HIP runtime error";
+        case SPT_ESINGULAR: return "Gram matrix product not positive definite";
+        case SPT_EWORKSPACE: return "workspace too small or misaligned";
+        case SPT_EUNSUPPORTED: return "unsupported order, rank or dtype combination";
+        case SPT_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+int spt_version(void) { return 100; }
+
+size_t spt_tensor_workspace_bytes(int d, const int64_t *dims, int64_t nnz, int vals_dtype) {
+    WsLayout L;
+    if (!layout(d, dims, nnz, vals_dtype, &L)) return 0;
+    return L.total;
+}
+
+int spt_tensor_create(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
+                      const int32_t *subs, const void *vals, int vals_dtype, void *ws,
+                      size_t ws_bytes, void *stream) {
+    if (out == nullptr) return SPT_EINVAL;
+    *out = nullptr;
+    WsLayout L;
+    if (d > SPT_MAX_ORDER && d >= 2) return SPT_EUNSUPPORTED;
+    if (!layout(d, dims, nnz, vals_dtype, &L)) return SPT_EINVAL;
+    if (nnz > 0 && (subs == nullptr || vals == nullptr)) return SPT_EINVAL;
+    if (ws == nullptr || ((uintptr_t)ws & 255u) != 0 || ws_bytes < L.total)
+        return SPT_EWORKSPACE;
+    spt_tensor *X = new (std::nothrow) spt_tensor;
+    if (!X) return SPT_EINVAL;
+    memset(X, 0, sizeof *X);
+    X->d = d;
+    for (int m = 0; m < d; ++m) X->dims[m] = dims[m];
+    for (int m = d; m < SPT_MAX_ORDER; ++m) X->dims[m] = 1;
+    X->P = nnz;
+    X->vdtype = vals_dtype;
+    X->rec_words = rec_words_for(d, vals_dtype);
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    X->ws = w;
+    X->ws_bytes = ws_bytes;
+    X->status = reinterpret_cast<SptStatusBlock *>(w + L.status);
+    X->rec = reinterpret_cast<int4 *>(w + L.rec);
+    for (int m = 0; m < d; ++m) {
+        X->perm[m] = reinterpret_cast<int32_t *>(w + L.perm + m * align256((size_t)nnz * 4));
+        X->skey[m] = reinterpret_cast<int32_t *>(w + L.skey + m * align256((size_t)nnz * 4));
+    }
+    X->tmp_keys = reinterpret_cast<int32_t *>(w + L.tmp_keys);
+    X->tmp_vals = reinterpret_cast<int32_t *>(w + L.tmp_vals);
+    X->hist = reinterpret_cast<uint32_t *>(w + L.hist);
+    X->scan_part = reinterpret_cast<uint32_t *>(w + L.scan_part);
+    X->red = reinterpret_cast<double *>(w + L.red);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, X->status);
+    if (hipGetLastError() != hipSuccess) {
+        delete X;
+        return SPT_EHIP;
+    }
+    if (nnz > 0) {
+        dim3 g((unsigned)ceil_div(nnz, kBlock)), b(kBlock);
+        const int64_t *dd = X->dims;
+        if (vals_dtype == SPT_F64) {
+            if (X->rec_words == 4)
+                hipLaunchKernelGGL((k_pack<double, 4>), g, b, 0, s, subs,
+                                   static_cast<const double *>(vals), d, nnz, X->rec,
+                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+            else
+                hipLaunchKernelGGL((k_pack<double, 8>), g, b, 0, s, subs,
+                                   static_cast<const double *>(vals), d, nnz, X->rec,
+                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+        } else {
+            if (X->rec_words == 4)
+                hipLaunchKernelGGL((k_pack<float, 4>), g, b, 0, s, subs,
+                                   static_cast<const float *>(vals), d, nnz, X->rec,
+                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+            else
+                hipLaunchKernelGGL((k_pack<float, 8>), g, b, 0, s, subs,
+                                   static_cast<const float *>(vals), d, nnz, X->rec,
+                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+        }
+        if (hipGetLastError() != hipSuccess) {
+            delete X;
+            return SPT_EHIP;
+        }
+    }
+    *out = X;
+    return SPT_OK;
+}
+
+int spt_tensor_status(const spt_tensor *X, void *stream) {
+    if (X == nullptr) return SPT_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SptStatusBlock h;
+    if (hipMemcpyAsync(&h, X->status, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return SPT_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPT_EHIP;
+    if (h.code != 0 && h.code != SPT_ERANGE) {
+        // clear a transient status (a range error is a property of the data and stays)
+        int32_t zero = 0;
+        if (hipMemcpyAsync(&X->status->code, &zero, sizeof zero, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return SPT_EHIP;
+    }
+    return h.code;
+}
+
+int spt_tensor_validate(const spt_tensor *X, int64_t *bad_entry, void *stream) {
+    if (X == nullptr) return SPT_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    SptStatusBlock h;
+    if (hipMemcpyAsync(&h, X->status, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return SPT_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return SPT_EHIP;
+    if (bad_entry) *bad_entry = (h.bad_entry == INT64_MAX) ? -1 : h.bad_entry;
+    return h.code;
+}
+
+int spt_tensor_permute(spt_tensor *X, int mode, void *stream) {
+    if (X == nullptr || mode < -1 || mode >= X->d) return SPT_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int n = 0; n < X->d; ++n) {
+        if (mode != -1 && n != mode) continue;
+        int rc = permute_mode(X, n, s);
+        if (rc) return rc;
+    }
+    return SPT_OK;
+}
+
+int spt_tensor_perm(const spt_tensor *X, int mode, const int32_t **perm, const int32_t **skey) {
+    if (X == nullptr || mode < 0 || mode >= X->d) return SPT_EINVAL;
+    if (!X->permuted[mode]) return SPT_ESTATE;
+    if (perm) *perm = X->perm[mode];
+    if (skey) *skey = X->skey[mode];
+    return SPT_OK;
+}
+
+int spt_tensor_info(const spt_tensor *X, int *d, int64_t *dims, int64_t *nnz, int *vals_dtype) {
+    if (X == nullptr) return SPT_EINVAL;
+    if (d) *d = X->d;
+    if (dims)
+        for (int m = 0; m < X->d; ++m) dims[m] = X->dims[m];
+    if (nnz) *nnz = X->P;
+    if (vals_dtype) *vals_dtype = X->vdtype;
+    return SPT_OK;
+}
+
+int spt_tensor_destroy(spt_tensor *X) {
+    delete X;
+    return SPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+"""GPU parity of the CP-ALS update, the fit, model values and the GCP Poisson loss/gradient
+against the FP64 CPU oracle, through the C ABI.
+
+Tolerances.  FP64 CP-ALS: a relative perturbation of 1e-15 in the factors of the 100 x 80 x 60
+workload stays below 4e-15 after 10 sweeps (the Hadamard Gram products there have condition
+numbers 8..35), so FP64 factors, weights and Grams are held to 1e-11 and the fit to 1e-12.
+FP32 storage: one mode update maps the MTTKRP error (<= 1e-6 measured) through Gamma^-1, so
+factors are held to max(1e-5, 1e-6 cond(Gamma)).  BF16 storage adds one rounding of 2^-9."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1809_09175_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / (nb if nb > 0 else 1.0)
+
+
+def _dev_tensor(X, dtype):
+    import paper_1809_09175_amd as spt
+    subs = torch.from_numpy(np.ascontiguousarray(X.subs, np.int32)).cuda()
+    vals = torch.from_numpy(np.ascontiguousarray(X.vals).astype(dtype)).cuda()
+    T = spt.SparseTensor(subs, vals, X.dims)
+    T.validate()
+    return T
+
+
+def _np(t):
+    return t.float().cpu().numpy().astype(np.float64) if t.dtype == torch.bfloat16 \
+        else t.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("algo", ["atomic", "permuted"])
+def test_cpals_small_fp64_ten_sweeps(gpu, algo):
+    import paper_1809_09175_amd as spt
+    X, A = datagen.cpals_small()
+    T = _dev_tensor(X, np.float64)
+    T.permute()
+    st = spt.CPState(T, [torch.from_numpy(a.copy()).cuda() for a in A])
+    Ao = [a.copy() for a in A]
+    lo = np.ones(16)
+    Go = np.stack([oracle.gram(a) for a in Ao])
+    assert _relerr(st.grams.cpu().numpy(), Go) < 1e-13
+    for it in range(10):
+        _log(f"cpals sweep {it} {algo}")
+        st.sweep(algo)
+        f_gpu, parts = st.fit(return_parts=True)
+        Ao, lo, Go = oracle.cp_als_sweep(X.subs, X.vals, X.dims, Ao, lo, Go)
+        f_ref, parts_ref = oracle.fit(X.subs, X.vals, X.dims, Ao, lo, return_parts=True)
+        for m in range(3):
+            assert _relerr(_np(st.factors[m]), Ao[m]) < 1e-11, (it, m)
+        assert _relerr(st.lam.cpu().numpy(), lo) < 1e-11
+        assert _relerr(st.grams.cpu().numpy(), Go) < 1e-11
+        assert abs(f_gpu - f_ref) < 1e-12, (it, f_gpu, f_ref)
+        assert np.allclose(parts, parts_ref, rtol=1e-12)
+
+
+def _skewed4_small():
+    X = datagen.skewed_tensor((2000, 500, 100, 365), 60_000, (1.2, 1.2, 0.0, 0.0), seed=3,
+                              distinct=True)
+    return X
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_cp_mode_update_low_precision(gpu, kind):
+    import paper_1809_09175_amd as spt
+    X = _skewed4_small()
+    R = 32
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    A32 = datagen.factors(X.dims, R, seed=8, dtype=np.float32)
+    dev = [torch.from_numpy(a.copy()).cuda() for a in A32]
+    if kind == "bf16":
+        dev = [spt.to_bf16(a) for a in dev]
+    st = spt.CPState(T, dev)
+    for n in range(4):
+        # the oracle starts from exactly the values the GPU holds before this mode update
+        Ain = [_np(f) for f in st.factors]
+        lin = st.lam.cpu().numpy()
+        Gin = st.grams.cpu().numpy()
+        assert _relerr(Gin, np.stack([a.T @ a for a in Ain])) < 1e-12
+        _log(f"mode update {kind} n={n}")
+        st.mode_update(n)
+        Ao, lo, Go = oracle.cp_als_mode(X.subs, X.vals, X.dims, Ain, lin, Gin, n)
+        Gam = np.ones((R, R))
+        for m in range(4):
+            if m != n:
+                Gam *= Gin[m]
+        cond = np.linalg.cond(Gam)
+        tol = max(1e-5, 1e-6 * cond)
+        if kind == "bf16":
+            tol += 2.0 ** -8
+        assert _relerr(_np(st.factors[n]), Ao[n]) < tol, (n, cond)
+        assert _relerr(st.lam.cpu().numpy(), lo) < tol
+        # the Gram is of the stored (rounded) factor, in FP64
+        stored = _np(st.factors[n])
+        assert _relerr(st.grams[n].cpu().numpy(), stored.T @ stored) < 1e-12
+
+
+def test_fit_matches_oracle_fp32_factors(gpu):
+    import paper_1809_09175_amd as spt
+    X = _skewed4_small()
+    R = 16
+    T = _dev_tensor(X, np.float32)
+    A32 = datagen.factors(X.dims, R, seed=9, dtype=np.float32)
+    st = spt.CPState(T, [torch.from_numpy(a).cuda() for a in A32])
+    st.lam = torch.linspace(0.5, 2.0, R, dtype=torch.float64, device="cuda")
+    f, parts = st.fit(return_parts=True)
+    f_ref, parts_ref = oracle.fit(X.subs, X.vals, X.dims, [a.astype(np.float64) for a in A32],
+                                  st.lam.cpu().numpy(), return_parts=True)
+    assert abs(f - f_ref) < 1e-12 * max(1.0, abs(f_ref))
+    assert np.allclose(parts, parts_ref, rtol=1e-12)
+
+
+def test_model_values(gpu):
+    import paper_1809_09175_amd as spt
+    X = _skewed4_small()
+    A = datagen.factors(X.dims, 24, seed=1, dtype=np.float64)
+    X.vals = X.vals.astype(np.float64)
+    T = _dev_tensor(X, np.float64)
+    lam = np.linspace(1.0, 2.0, 24)
+    m = spt.model_values(T, [torch.from_numpy(a).cuda() for a in A],
+                         torch.from_numpy(lam).cuda())
+    assert _relerr(m.cpu().numpy(), oracle.model_values(X.subs, X.dims, A, lam)) < 1e-13
+
+
+def test_singular_gram_reported(gpu):
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import SptError
+    dims = (4, 3, 3)
+    cells = np.array(list(itertools.product(*[range(I) for I in dims])), dtype=np.int32)
+    X = datagen.CooTensor(cells, np.ones(len(cells)), dims)
+    T = _dev_tensor(X, np.float64)
+    st = spt.CPState(T, [torch.ones(I, 2, dtype=torch.float64, device="cuda") for I in dims])
+    st.mode_update(0)
+    with pytest.raises(SptError) as e:
+        st.fit()
+    assert e.value.code == -4
+    assert T.status() == 0          # the status was cleared once reported
+
+
+def test_exact_low_rank_recovery(gpu):
+    import paper_1809_09175_amd as spt
+    rng = np.random.default_rng(31)
+    dims = (12, 10, 8)
+    R = 3
+    Tr = [rng.standard_normal((I, R)) for I in dims]
+    Xd = np.einsum("ir,jr,kr->ijk", *Tr)
+    cells = np.array(list(itertools.product(*[range(I) for I in dims])), dtype=np.int32)
+    X = datagen.CooTensor(cells, Xd[cells[:, 0], cells[:, 1], cells[:, 2]], dims)
+    T = _dev_tensor(X, np.float64)
+    T.permute()
+    A0 = [t + 1e-2 * rng.standard_normal(t.shape) for t in Tr]
+    st = spt.CPState(T, [torch.from_numpy(a).cuda() for a in A0])
+    prev = -1.0
+    for it in range(300):
+        st.sweep()
+        if it % 10 == 9:
+            A = [_np(f) for f in st.factors]
+            M = np.einsum("r,ir,jr,kr->ijk", st.lam.cpu().numpy(), *A)
+            fit = 1.0 - np.linalg.norm(Xd - M) / np.linalg.norm(Xd)
+            if fit > 1.0 - 1e-10 and abs(fit - prev) < 1e-15:
+                break
+            prev = fit
+    assert fit > 1.0 - 1e-10
+
+
+# -------------------------------------------------------------------------------------- GCP
+
+def _gcp_case(dtype):
+    X, A = datagen.gcp_counts(scale=2e-4, dims=(200, 100, 50), R=8)
+    X.vals = X.vals.astype(dtype)
+    A = [a.astype(dtype) for a in A]
+    return X, A
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_gcp_poisson_forward_backward(gpu, kind):
+    import paper_1809_09175_amd as spt
+    dt = np.float64 if kind == "f64" else np.float32
+    X, A = _gcp_case(dt)
+    T = _dev_tensor(X, dt)
+    T.permute()
+    rng = np.random.default_rng(2)
+    w = (rng.random(X.nnz) + 0.5).astype(dt)
+    wd = torch.from_numpy(w).cuda()
+    facs = [torch.from_numpy(a).cuda().requires_grad_(True) for a in A]
+    loss = spt.GCPPoissonLoss.apply(T, wd, *facs)
+    (3.0 * loss).backward()
+    loss_ref, g_ref = oracle.gcp_poisson(X.subs, X.vals, X.dims, [a.astype(np.float64) for a in A],
+                                         w.astype(np.float64))
+    tol = 1e-12 if kind == "f64" else 1e-5
+    assert abs(loss.item() - loss_ref) < tol * abs(loss_ref)
+    gtol = 1e-12 if kind == "f64" else 1e-4
+    for n in range(3):
+        assert _relerr(facs[n].grad.cpu().numpy(), 3.0 * g_ref[n]) < gtol, n
+
+
+def test_gcp_gradcheck_fp64(gpu):
+    import paper_1809_09175_amd as spt
+    X, A = datagen.gcp_counts(scale=6e-7, dims=(9, 7, 5), R=3)
+    X.vals = X.vals.astype(np.float64)
+    T = _dev_tensor(X, np.float64)
+    facs = tuple(torch.from_numpy(a.astype(np.float64)).cuda().requires_grad_(True) for a in A)
+    assert torch.autograd.gradcheck(lambda *f: spt.GCPPoissonLoss.apply(T, None, *f), facs,
+                                    eps=1e-6, atol=1e-7, rtol=1e-6)

@@ -1,0 +1,265 @@
+"""GPU parity of the permutation build and both MTTKRP kernels against the FP64 CPU oracle,
+through the C ABI.  Tolerances (relative Frobenius error of V): 1e-12 for FP64, 1e-5 for FP32,
+2e-2 for BF16 factors against the unrounded FP64 factors."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1809_09175_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2}
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / (nb if nb > 0 else 1.0)
+
+
+def _dev_tensor(X, dtype):
+    import paper_1809_09175_amd as spt
+    subs = torch.from_numpy(np.ascontiguousarray(X.subs, np.int32)).cuda()
+    vals = torch.from_numpy(np.ascontiguousarray(X.vals).astype(dtype)).cuda()
+    T = spt.SparseTensor(subs, vals, X.dims)
+    T.validate()
+    return T
+
+
+def _factors(dims, R, seed, kind):
+    A64 = datagen.factors(dims, R, seed, np.float64)
+    if kind == "f64":
+        dev = [torch.from_numpy(a).cuda() for a in A64]
+        ref = A64
+    elif kind == "f32":
+        a32 = [a.astype(np.float32) for a in A64]
+        dev = [torch.from_numpy(a).cuda() for a in a32]
+        ref = [a.astype(np.float64) for a in a32]
+    else:
+        a32 = [a.astype(np.float32) for a in A64]
+        dev = [torch.from_numpy(a).cuda().to(torch.bfloat16) for a in a32]
+        ref = [a.astype(np.float64) for a in a32]          # unrounded factors
+    return dev, ref
+
+
+def _small(kind, dims, nnz, skew, seed):
+    X = datagen.skewed_tensor(dims, nnz, skew, seed)
+    if kind == "f64":
+        X.vals = X.vals.astype(np.float64)
+    return X
+
+
+# --------------------------------------------------------------------------------- permutation
+
+@pytest.mark.parametrize("dims,nnz,skew", [
+    ((1, 7, 300), 1000, (0.0, 1.1, 1.1)),
+    ((200, 3000, 70000), 50_001, (1.1, 1.1, 0.0)),
+    ((2, 5_000_000, 17), 200_003, (0.0, 1.2, 0.0)),
+    ((65536, 256, 257), 131_072, (0.0, 0.0, 0.0)),
+])
+def test_permutation_bit_exact(gpu, dims, nnz, skew):
+    _log(f"perm dims={dims} nnz={nnz}")
+    X = datagen.skewed_tensor(dims, nnz, skew, seed=nnz)
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    torch.cuda.synchronize()
+    for n in range(3):
+        p_ref, k_ref = oracle.perm(X.subs, X.dims, n)
+        p, k = T.perm(n)
+        assert np.array_equal(p.cpu().numpy(), p_ref)
+        assert np.array_equal(k.cpu().numpy(), k_ref)
+
+
+def test_permutation_empty(gpu):
+    X = datagen.CooTensor(np.zeros((0, 3), np.int32), np.zeros(0, np.float32), (4, 5, 6))
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    torch.cuda.synchronize()
+    assert T.perm(0)[0].numel() == 0
+
+
+# ------------------------------------------------------------------------------------- MTTKRP
+
+CASES = [
+    # (kind, dims, nnz, skew, R)
+    ("f32", (500, 400, 30), 100_000, (1.1, 1.1, 1.1), 32),
+    ("f32", (500, 400, 30), 77_777, (1.1, 1.1, 1.1), 16),
+    ("f32", (3000, 20, 9), 50_001, (1.2, 0.0, 1.1), 64),
+    ("f32", (100, 90, 80), 20_000, (0.0, 0.0, 0.0), 7),
+    ("f32", (50, 60, 70, 8), 40_000, (1.2, 1.2, 0.0, 0.0), 32),
+    ("f32", (40, 30, 20, 10, 5), 30_000, (1.1, 0.0, 0.0, 0.0, 0.0), 24),
+    ("f32", (300, 200), 10_000, (1.1, 1.1), 48),
+    ("f32", (1000, 1000, 1000), 60_000, (1.1, 1.1, 1.1), 128),
+    ("f32", (200, 150, 100), 30_000, (1.1, 1.1, 1.1), 256),
+    ("f64", (100, 80, 60), 10_000, (0.0, 0.0, 0.0), 16),
+    ("f64", (500, 400, 30), 50_000, (1.1, 1.1, 1.1), 32),
+    ("f64", (60, 50, 40, 30), 20_000, (1.1, 0.0, 1.1, 0.0), 64),
+    ("bf16", (500, 400, 30), 100_000, (1.1, 1.1, 1.1), 32),
+    ("bf16", (3000, 20, 9), 50_001, (1.2, 0.0, 1.1), 64),
+    ("bf16", (100, 90, 80), 20_000, (0.0, 0.0, 0.0), 9),
+]
+
+
+@pytest.mark.parametrize("algo", ["atomic", "permuted"])
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-d{len(c[1])}-R{c[4]}-P{c[2]}" for c in CASES])
+def test_mttkrp_parity(gpu, case, algo):
+    import paper_1809_09175_amd as spt
+    kind, dims, nnz, skew, R = case
+    _log(f"mttkrp {kind} dims={dims} nnz={nnz} R={R} algo={algo}")
+    X = _small(kind, dims, nnz, skew, seed=nnz + R)
+    T = _dev_tensor(X, np.float64 if kind == "f64" else np.float32)
+    T.permute()
+    dev, ref = _factors(dims, R, seed=R, kind=kind)
+    lam = np.linspace(0.5, 1.5, R)
+    lam_d = torch.from_numpy(lam).cuda()
+    for n in range(len(dims)):
+        V_ref = oracle.mttkrp(X.subs, X.vals, dims, ref, n, lam)
+        for chunk in (64, 2048):
+            V = spt.mttkrp(T, dev, n, lam=lam_d, algo=algo, chunk=chunk)
+            torch.cuda.synchronize()
+            err = _relerr(V.cpu().numpy(), V_ref)
+            assert err < TOL[kind], (n, chunk, err)
+
+
+def _configs_for(R, kind):
+    out = []
+    for lanes, cols in [(8, 1), (16, 1), (32, 1), (64, 1), (8, 2), (16, 2), (32, 2), (64, 2),
+                        (16, 4), (64, 4)]:
+        if lanes * cols >= R and R % cols == 0:
+            out.append((lanes, cols))
+    return out
+
+
+@pytest.mark.parametrize("kind,R", [("f32", 16), ("f32", 32), ("bf16", 32), ("f64", 16)])
+def test_mttkrp_every_lane_config(gpu, kind, R):
+    import paper_1809_09175_amd as spt
+    dims = (700, 500, 40)
+    X = _small(kind, dims, 65_537, (1.1, 1.1, 1.1), seed=5)
+    T = _dev_tensor(X, np.float64 if kind == "f64" else np.float32)
+    T.permute()
+    dev, ref = _factors(dims, R, seed=3, kind=kind)
+    for n in range(3):
+        V_ref = oracle.mttkrp(X.subs, X.vals, dims, ref, n)
+        for lanes, cols in _configs_for(R, kind):
+            for algo in ("atomic", "permuted"):
+                _log(f"cfg {kind} R={R} n={n} lanes={lanes} cols={cols} {algo}")
+                V = spt.mttkrp(T, dev, n, algo=algo, lanes=lanes, cols=cols, chunk=512)
+                torch.cuda.synchronize()
+                assert _relerr(V.cpu().numpy(), V_ref) < TOL[kind], (lanes, cols, algo)
+
+
+def test_bf16_against_rounded_factors_is_fp32_tight(gpu):
+    """With the factors the kernel actually sees (BF16 values widened exactly), only FP32
+    accumulation separates kernel and oracle."""
+    import paper_1809_09175_amd as spt
+    dims = (500, 400, 30)
+    X = _small("bf16", dims, 100_000, (1.1, 1.1, 1.1), seed=9)
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    dev, _ = _factors(dims, 32, seed=4, kind="bf16")
+    rounded = [d.float().cpu().numpy().astype(np.float64) for d in dev]
+    for n in range(3):
+        V_ref = oracle.mttkrp(X.subs, X.vals, dims, rounded, n)
+        for algo in ("atomic", "permuted"):
+            V = spt.mttkrp(T, dev, n, algo=algo)
+            torch.cuda.synchronize()
+            assert _relerr(V.cpu().numpy(), V_ref) < 1e-5
+
+
+def test_mttkrp_edge_cases(gpu):
+    import paper_1809_09175_amd as spt
+    # empty tensor -> zeros
+    X = datagen.CooTensor(np.zeros((0, 3), np.int32), np.zeros(0, np.float32), (4, 5, 6))
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    dev, _ = _factors(X.dims, 8, 1, "f32")
+    for algo in ("atomic", "permuted"):
+        V = spt.mttkrp(T, dev, 1, algo=algo)
+        torch.cuda.synchronize()
+        assert V.shape == (5, 8) and not V.cpu().numpy().any()
+    # a single entry, a mode of length one, replacement values
+    X = datagen.CooTensor(np.array([[3, 0, 2]], np.int32), np.array([2.5], np.float32), (4, 1, 6))
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    dev, ref = _factors(X.dims, 8, 2, "f32")
+    y = torch.tensor([-1.0], device="cuda")
+    for n in range(3):
+        for algo in ("atomic", "permuted"):
+            V = spt.mttkrp(T, dev, n, algo=algo)
+            V2 = spt.mttkrp(T, dev, n, algo=algo, vals=y)
+            torch.cuda.synchronize()
+            assert _relerr(V.cpu().numpy(), oracle.mttkrp(X.subs, X.vals, X.dims, ref, n)) < 1e-6
+            assert _relerr(V2.cpu().numpy(), oracle.mttkrp(X.subs, [-1.0], X.dims, ref, n)) < 1e-6
+
+
+def test_errors_reported(gpu):
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import SptError
+    X = datagen.CooTensor(np.array([[0, 0, 0], [1, 7, 0]], np.int32),
+                          np.ones(2, np.float32), (2, 5, 3))
+    subs = torch.from_numpy(X.subs).cuda()
+    vals = torch.from_numpy(X.vals).cuda()
+    T = spt.SparseTensor(subs, vals, X.dims)
+    with pytest.raises(SptError) as e:
+        T.validate()
+    assert e.value.code == -2 and "first bad entry 1" in str(e.value)
+    X = datagen.CooTensor(np.array([[0, 0, 0]], np.int32), np.ones(1, np.float32), (2, 5, 3))
+    T = _dev_tensor(X, np.float32)
+    dev, _ = _factors(X.dims, 4, 1, "f32")
+    with pytest.raises(SptError) as e:
+        spt.mttkrp(T, dev, 0, algo="permuted")
+    assert e.value.code == -7
+    with pytest.raises(SptError) as e:
+        spt.mttkrp(T, dev, 3, out=torch.empty(4, 4, device="cuda"))   # mode >= d
+    assert e.value.code == -1
+    with pytest.raises(SptError) as e:
+        spt.mttkrp(T, [torch.empty(2, 300, device="cuda")] * 3, 0)     # R > 256
+    assert e.value.code == -1
+    dev64, _ = _factors(X.dims, 4, 1, "f64")
+    with pytest.raises(SptError) as e:
+        spt.mttkrp(T, dev64, 0)
+    assert e.value.code == -6
+
+
+# ------------------------------------------------------------------ full-size sampled parity
+
+def _sampled_rows(X, n, rows):
+    mask = np.isin(X.subs[:, n], rows)
+    return X.subs[mask], X.vals[mask]
+
+
+@pytest.mark.slow
+def test_powerlaw3_full_size_sampled(gpu):
+    """The 1e8-entry power-law tensor at R=32, in the benchmark's launch configuration:
+    selected rows of V (the hottest row of each mode, a ragged tail of random rows) against
+    the oracle on exactly the entries that feed them."""
+    import paper_1809_09175_amd as spt
+    _log("powerlaw3 full size: generating")
+    X = datagen.powerlaw3()
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    R = 32
+    dev, ref = _factors(X.dims, R, seed=7, kind="f32")
+    rng = np.random.default_rng(0)
+    for n in range(3):
+        counts = np.bincount(X.subs[:, n], minlength=X.dims[n])
+        hot = int(np.argmax(counts))
+        rows = np.unique(np.concatenate([[hot], rng.integers(0, X.dims[n], size=40)]))
+        s, v = _sampled_rows(X, n, rows)
+        V_ref = oracle.mttkrp(s, v, X.dims, ref, n)[rows]
+        for algo in ("atomic", "permuted"):
+            _log(f"powerlaw3 n={n} {algo}")
+            V = spt.mttkrp(T, dev, n, algo=algo)
+            torch.cuda.synchronize()
+            got = V[torch.from_numpy(rows).cuda()].cpu().numpy()
+            assert _relerr(got, V_ref) < TOL["f32"], (n, algo)
+            # the hot row alone (the FP32 accuracy risk: 12.7% of all entries)
+            assert _relerr(got[rows == hot], V_ref[rows == hot]) < TOL["f32"]
