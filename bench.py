@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--quick", action="store_true", help="skip the extra workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: R=32 permuted and atomic, 2 steps each, plus "
+                         "one triad over 3 x 1 GiB (the counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -154,9 +157,18 @@ def main():
                 "wall_s": wall}
 
     R = args.rank
+    if args.profile:
+        args.steps, args.warmup, args.quick, args.no_cpu = 2, 1, True, True
+        n = 1 << 28
+        a = torch.empty(n, dtype=torch.float32, device=dev)
+        b = torch.rand(n, dtype=torch.float32, device=dev)
+        c = torch.rand(n, dtype=torch.float32, device=dev)
+        spt.stream_triad(a, b, c)
+        torch.cuda.synchronize()
+        del a, b, c
     main_res = measure(R, "permuted", args.steps, args.warmup)
     log(f"R={R} permuted: {main_res['ms_per_step']:.3f} ms/step, {main_res['gbs']:.0f} GB/s")
-    atomic_res = measure(R, "atomic", max(3, args.steps // 2), 2)
+    atomic_res = measure(R, "atomic", max(2, args.steps // 2), 1 if args.profile else 2)
     log(f"R={R} atomic:   {atomic_res['ms_per_step']:.3f} ms/step, {atomic_res['gbs']:.0f} GB/s")
 
     extras = {}
@@ -224,7 +236,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        S = 20_000_000
+        S = 40_000_000
         A = [a.astype(np.float64) for a in datagen.factors(X.dims, R, seed=7, dtype=np.float32)]
         sub_s, sub_v = X.subs[:S], X.vals[:S]
         t = time.perf_counter()

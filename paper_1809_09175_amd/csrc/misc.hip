@@ -10,14 +10,36 @@ __global__ __launch_bounds__(kBlock) void k_f32_to_bf16(const float *__restrict_
         out[i] = f32_to_bf16_rne(in[i]);
 }
 
+// Each thread handles kTriadUnroll float4 elements, strided by the block size so every load and
+// store instruction of a wave covers 1 KiB of contiguous memory; the output is written with
+// non-temporal stores (it is not read again).
+constexpr int kTriadUnroll = 4;
+
 __global__ __launch_bounds__(kBlock) void k_triad(float4 *__restrict__ a,
                                                   const float4 *__restrict__ b,
                                                   const float4 *__restrict__ c, float s,
                                                   int64_t nq) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nq; i += stride) {
-        float4 x = b[i], y = c[i];
-        a[i] = make_float4(x.x + s * y.x, x.y + s * y.y, x.z + s * y.z, x.w + s * y.w);
+    const int64_t base = (int64_t)blockIdx.x * kBlock * kTriadUnroll + threadIdx.x;
+    float4 x[kTriadUnroll], y[kTriadUnroll];
+#pragma unroll
+    for (int k = 0; k < kTriadUnroll; ++k) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        if (i < nq) {
+            x[k] = b[i];
+            y[k] = c[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kTriadUnroll; ++k) {
+        const int64_t i = base + (int64_t)k * kBlock;
+        if (i < nq) {
+            float4 r = make_float4(x[k].x + s * y[k].x, x[k].y + s * y[k].y, x[k].z + s * y[k].z,
+                                   x[k].w + s * y[k].w);
+            __builtin_nontemporal_store(r.x, &a[i].x);
+            __builtin_nontemporal_store(r.y, &a[i].y);
+            __builtin_nontemporal_store(r.z, &a[i].z);
+            __builtin_nontemporal_store(r.w, &a[i].w);
+        }
     }
 }
 
@@ -48,8 +70,7 @@ extern "C" int spt_stream_triad(float *a, const float *b, const float *c, float 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t nq = n / 4;
     if (nq > 0) {
-        int64_t blocks = ceil_div(nq, kBlock);
-        if (blocks > 256 * 32) blocks = 256 * 32;
+        const int64_t blocks = ceil_div(nq, (int64_t)kBlock * kTriadUnroll);
         hipLaunchKernelGGL(k_triad, dim3((unsigned)blocks), dim3(kBlock), 0, st,
                            reinterpret_cast<float4 *>(a), reinterpret_cast<const float4 *>(b),
                            reinterpret_cast<const float4 *>(c), s, nq);
