@@ -122,7 +122,8 @@ int spt_tensor_destroy(spt_tensor *X);
  *   mode     n, 0 <= n < d
  *   R        rank, 1 .. 256
  *   factors  host array of d device pointers, A^(m) is I_m x R row-major of fdtype; the entry
- *            for m == n is not read and may be NULL
+ *            for m == n is not read and may be NULL; each matrix must be smaller than 4 GiB
+ *            (SPT_EUNSUPPORTED otherwise: rows are addressed with 32-bit byte offsets)
  *   fdtype   SPT_F64 (needs F64 tensor values), SPT_F32 or SPT_BF16 (need F32 values)
  *   lambda   device R doubles, or NULL for all ones
  *   vals     device, NULL to use the tensor's values, else P replacement values in the tensor's

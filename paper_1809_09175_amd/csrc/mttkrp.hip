@@ -24,11 +24,14 @@ int zero_words(void *p, int64_t nwords, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }
 
+// (lanes per entry, columns per lane) pairs with compiled kernels
 static bool cfg_supported(int G, int CPL) {
-    switch (G * 8 + CPL) {
-        case 8 * 8 + 1: case 16 * 8 + 1: case 32 * 8 + 1: case 64 * 8 + 1:
-        case 8 * 8 + 2: case 16 * 8 + 2: case 32 * 8 + 2: case 64 * 8 + 2:
-        case 16 * 8 + 4: case 64 * 8 + 4:
+    switch (G * 16 + CPL) {
+        case 4 * 16 + 4: case 4 * 16 + 8:
+        case 8 * 16 + 1: case 8 * 16 + 2: case 8 * 16 + 4: case 8 * 16 + 8:
+        case 16 * 16 + 1: case 16 * 16 + 2: case 16 * 16 + 4: case 16 * 16 + 8:
+        case 32 * 16 + 1: case 32 * 16 + 2:
+        case 64 * 16 + 1: case 64 * 16 + 4:
             return true;
         default:
             return false;
@@ -66,7 +69,7 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
         if (cpl == 4 && R % 4 != 0) cpl = 2;
         if (cpl == 2 && R % 2 != 0) cpl = 1;
     }
-    if (cpl != 1 && cpl != 2 && cpl != 4) return SPT_EINVAL;
+    if (cpl != 1 && cpl != 2 && cpl != 4 && cpl != 8) return SPT_EINVAL;
     if (R % cpl != 0) return SPT_EUNSUPPORTED;
     int G = t.lanes_per_nnz;
     if (G == 0) {
@@ -134,7 +137,14 @@ int check_mttkrp_args(const spt_tensor *X, int mode, int R, const void *const *f
         return SPT_EINVAL;
     int rc = check_factors(X, mode, factors);
     if (rc) return rc;
-    return check_dtypes(X, fdtype);
+    rc = check_dtypes(X, fdtype);
+    if (rc) return rc;
+    // factor rows are addressed with 32-bit byte offsets
+    const uint64_t fbytes = fdtype == SPT_F64 ? 8 : (fdtype == SPT_F32 ? 4 : 2);
+    for (int m = 0; m < X->d; ++m)
+        if (m != mode && (uint64_t)X->dims[m] * (uint64_t)R * fbytes >= (1ull << 32))
+            return SPT_EUNSUPPORTED;
+    return SPT_OK;
 }
 
 }  // namespace spt

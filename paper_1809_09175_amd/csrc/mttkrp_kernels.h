@@ -53,12 +53,12 @@ __device__ __forceinline__ void rec_set_value(int *w, VT v) {
     }
 }
 
-template <int D, int RW>
-__device__ __forceinline__ int rec_sub(const int *w, int n) {
-    int k = w[0];
-#pragma unroll
-    for (int m = 1; m < D; ++m) k = (m == n) ? w[m] : k;
-    return k;
+// Mode-n subscript of a record staged in LDS.  Read with its own LDS load at a run-time word
+// offset: selecting it from the record's registers by the run-time mode makes the compiler
+// spill the record to scratch memory to index it.
+template <int RW>
+__device__ __forceinline__ int lds_sub(const int4 *q, int n) {
+    return reinterpret_cast<const int *>(q)[n];
 }
 
 // CPL consecutive factor entries, widened to the accumulation type
@@ -71,12 +71,20 @@ __device__ __forceinline__ void load_cols(const FT *__restrict__ p, AT *out) {
             uint32_t v = *reinterpret_cast<const uint32_t *>(p);
             out[0] = bf16_bits_to_f32(v & 0xffffu);
             out[1] = bf16_bits_to_f32(v >> 16);
-        } else {
+        } else if constexpr (CPL == 4) {
             uint2 v = *reinterpret_cast<const uint2 *>(p);
             out[0] = bf16_bits_to_f32(v.x & 0xffffu);
             out[1] = bf16_bits_to_f32(v.x >> 16);
             out[2] = bf16_bits_to_f32(v.y & 0xffffu);
             out[3] = bf16_bits_to_f32(v.y >> 16);
+        } else {
+            uint4 v = *reinterpret_cast<const uint4 *>(p);
+            const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                out[2 * h] = bf16_bits_to_f32(q[h] & 0xffffu);
+                out[2 * h + 1] = bf16_bits_to_f32(q[h] >> 16);
+            }
         }
     } else if constexpr (sizeof(FT) == 4) {
         if constexpr (CPL == 1) {
@@ -86,11 +94,14 @@ __device__ __forceinline__ void load_cols(const FT *__restrict__ p, AT *out) {
             out[0] = v.x;
             out[1] = v.y;
         } else {
-            float4 v = *reinterpret_cast<const float4 *>(p);
-            out[0] = v.x;
-            out[1] = v.y;
-            out[2] = v.z;
-            out[3] = v.w;
+#pragma unroll
+            for (int h = 0; h < CPL; h += 4) {
+                float4 v = *reinterpret_cast<const float4 *>(p + h);
+                out[h] = v.x;
+                out[h + 1] = v.y;
+                out[h + 2] = v.z;
+                out[h + 3] = v.w;
+            }
         }
     } else {
         if constexpr (CPL == 1) {
@@ -110,8 +121,10 @@ template <class AT, int CPL>
 __device__ __forceinline__ void store_cols(AT *__restrict__ p, const AT *v) {
     if constexpr (sizeof(AT) == 4 && CPL == 2) {
         *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
-    } else if constexpr (sizeof(AT) == 4 && CPL == 4) {
-        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (sizeof(AT) == 4 && CPL >= 4) {
+#pragma unroll
+        for (int h = 0; h < CPL; h += 4)
+            *reinterpret_cast<float4 *>(p + h) = make_float4(v[h], v[h + 1], v[h + 2], v[h + 3]);
     } else {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) p[c] = v[c];
@@ -126,9 +139,12 @@ __device__ __forceinline__ void atomic_cols(AT *__restrict__ p, const AT *v) {
 
 // Product row of one entry: t[c] = x * lambda_j * prod_{m != n} A^(m)(l_m, j), for this lane's
 // columns j = col0 .. col0+CPL-1 (multiply order as in Sec. 4.1: x times the weight first,
-// then each other mode in increasing order).
+// then each other mode in increasing order).  Factor rows are addressed with 32-bit byte
+// offsets from the (wave-uniform) matrix base, so each gather needs one offset register and
+// the hardware's scalar-base addressing; every factor matrix must be smaller than 4 GiB.
 template <int D, int RW, int CPL, class FT, class VT, class AT>
-__device__ __forceinline__ void entry_product(const int *w, int n, int R, int col0, bool colok,
+__device__ __forceinline__ void entry_product(const int *w, int n, uint32_t rowbytes,
+                                              uint32_t colbytes, bool colok,
                                               const FactorSet<FT> &A, const AT *lam, AT *t) {
     const AT x = (AT)rec_value<VT, RW>(w);
 #pragma unroll
@@ -138,13 +154,33 @@ __device__ __forceinline__ void entry_product(const int *w, int n, int R, int co
         for (int m = 0; m < D; ++m) {
             if (m != n) {
                 AT f[CPL];
-                load_cols<FT, CPL, AT>(A.p[m] + (int64_t)w[m] * R + col0, f);
+                const uint32_t off = (uint32_t)w[m] * rowbytes + colbytes;
+                load_cols<FT, CPL, AT>(
+                    reinterpret_cast<const FT *>(reinterpret_cast<const char *>(A.p[m]) + off), f);
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) t[c] *= f[c];
             }
         }
     }
 }
+
+template <int RQ>
+__device__ __forceinline__ void lds_record(const int4 *q, int *w) {
+    int4 a = q[0];
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    if constexpr (RQ == 2) {
+        int4 b = q[1];
+        w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+    }
+}
+
+// entries gathered ahead per lane group: enough loads in flight to cover the gather latency
+// while the registers still allow 6-8 waves per SIMD
+template <int CPL, int G>
+struct UnrollFor {
+    static constexpr int raw = 16 / CPL;
+    static constexpr int value = raw < G ? raw : G;
+};
 
 template <int D, int G, int CPL, class FT, class VT, class AT>
 __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
@@ -153,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
     AT *__restrict__ V, int chunk) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int NG = kWave / G;
-    constexpr int U = (CPL >= 4) ? 4 : 8;
+    constexpr int U = UnrollFor<CPL, G>::value;
     __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
     __shared__ AT s_part[kBlock / kWave][2 * NG][G * CPL];
     __shared__ int s_pkey[kBlock / kWave][2 * NG];
@@ -162,6 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
     const bool colok = col0 < R;
+    const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
     const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
     if (c0 >= P) return;  // whole wavefront leaves together
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
@@ -171,6 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
     const int glen = ge > gb ? (int)(ge - gb) : 0;
     const int wlen = (int)((c1 - c0) < S ? (c1 - c0) : S);
     const int nb = (wlen + G - 1) / G;
+    const int32_t *gperm = perm + gb;
 
     AT lam[CPL];
 #pragma unroll
@@ -181,41 +219,62 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
         s_pkey[wave][2 * g + 1] = -1;
     }
 
+    // software pipeline: the records of batch b+1 and the permutation entries of batch b+2
+    // are in flight while batch b is processed
+    int4 rc0 = make_int4(0, 0, 0, 0), rc1 = rc0;
+    VT vo = 0;
+    int pn = -1;
+    if (gl < glen) {
+        const int p = gperm[gl];
+        rc0 = rec[(int64_t)p * RQ];
+        if constexpr (RQ == 2) rc1 = rec[(int64_t)p * RQ + 1];
+        if (vovr != nullptr) vo = vovr[p];
+    }
+    if (G + gl < glen) pn = gperm[G + gl];
+
     int key = -1, first_key = -1;
     AT acc[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[c] = 0;
 
     for (int b = 0; b < nb; ++b) {
-        const int off = b * G + gl;
-        if (off < glen) {
-            const int p = perm[gb + off];
-            const int4 *r = rec + (int64_t)p * RQ;
-            s_rec[wave][lane * RQ] = r[0];
-            if constexpr (RQ == 2) s_rec[wave][lane * RQ + 1] = r[1];
+        if (b * G + gl < glen) {
+            s_rec[wave][lane * RQ] = rc0;
+            if constexpr (RQ == 2) s_rec[wave][lane * RQ + 1] = rc1;
             if (vovr != nullptr)
-                rec_set_value<VT, RW>(reinterpret_cast<int *>(&s_rec[wave][lane * RQ]), vovr[p]);
+                rec_set_value<VT, RW>(reinterpret_cast<int *>(&s_rec[wave][lane * RQ]), vo);
         }
         wave_sync();
+        if (pn >= 0) {
+            rc0 = rec[(int64_t)pn * RQ];
+            if constexpr (RQ == 2) rc1 = rec[(int64_t)pn * RQ + 1];
+            if (vovr != nullptr) vo = vovr[pn];
+        }
+        pn = ((b + 2) * G + gl < glen) ? gperm[(b + 2) * G + gl] : -1;
+
         const int cnt = glen - b * G < G ? glen - b * G : G;
+        const int4 *sr = &s_rec[wave][g * G * RQ];
         for (int s0 = 0; s0 < cnt; s0 += U) {
             AT t[U][CPL];
             int kk[U];
+            if (s0 + U <= cnt) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int s = s0 + u;
-                kk[u] = -1;
-                if (s < cnt) {
+                for (int u = 0; u < U; ++u) {
                     int w[RW];
-                    const int4 *q = &s_rec[wave][(g * G + s) * RQ];
-                    int4 a = q[0];
-                    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
-                    if constexpr (RQ == 2) {
-                        int4 bq = q[1];
-                        w[4] = bq.x; w[5] = bq.y; w[6] = bq.z; w[7] = bq.w;
+                    lds_record<RQ>(sr + (s0 + u) * RQ, w);
+                    kk[u] = lds_sub<RW>(sr + (s0 + u) * RQ, n);
+                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, rowbytes, colbytes, colok, A, lam, t[u]);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    kk[u] = -1;
+                    if (s0 + u < cnt) {
+                        int w[RW];
+                        lds_record<RQ>(sr + (s0 + u) * RQ, w);
+                        kk[u] = lds_sub<RW>(sr + (s0 + u) * RQ, n);
+                        entry_product<D, RW, CPL, FT, VT, AT>(w, n, rowbytes, colbytes, colok, A, lam, t[u]);
                     }
-                    kk[u] = rec_sub<D, RW>(w, n);
-                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, R, col0, colok, A, lam, t[u]);
                 }
             }
 #pragma unroll
@@ -284,7 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int NG = kWave / G;
     constexpr int RP = G * CPL;
-    constexpr int U = (CPL >= 4) ? 4 : 8;
+    constexpr int U = UnrollFor<CPL, G>::value;
+    (void)NG;
     extern __shared__ int4 smem4[];
     int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
     int *hkeys = reinterpret_cast<int *>(smem4 + (kBlock / kWave) * kWave * RQ);
@@ -295,6 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
     const bool colok = col0 < R;
+    const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
     for (int i = tid; i < H; i += kBlock) hkeys[i] = -1;
     for (int i = tid; i < H * RP; i += kBlock) hvals[i] = 0;
     __syncthreads();
@@ -329,15 +390,9 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
                 kk[u] = -1;
                 if (s < cnt) {
                     int w[RW];
-                    const int4 *q = &s_rec[(g * G + s) * RQ];
-                    int4 a = q[0];
-                    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
-                    if constexpr (RQ == 2) {
-                        int4 bq = q[1];
-                        w[4] = bq.x; w[5] = bq.y; w[6] = bq.z; w[7] = bq.w;
-                    }
-                    kk[u] = rec_sub<D, RW>(w, n);
-                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, R, col0, colok, A, lam, t[u]);
+                    lds_record<RQ>(&s_rec[(g * G + s) * RQ], w);
+                    kk[u] = lds_sub<RW>(&s_rec[(g * G + s) * RQ], n);
+                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, rowbytes, colbytes, colok, A, lam, t[u]);
                 }
             }
 #pragma unroll
@@ -430,17 +485,21 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
 
 template <int D, class FT, class VT, class AT>
 int launch_d(const MttkrpArgs &a, const FactorSet<FT> &A, int G, int CPL) {
-    switch (G * 8 + CPL) {
-        case 8 * 8 + 1: return launch_cfg<D, 8, 1, FT, VT, AT>(a, A);
-        case 16 * 8 + 1: return launch_cfg<D, 16, 1, FT, VT, AT>(a, A);
-        case 32 * 8 + 1: return launch_cfg<D, 32, 1, FT, VT, AT>(a, A);
-        case 64 * 8 + 1: return launch_cfg<D, 64, 1, FT, VT, AT>(a, A);
-        case 8 * 8 + 2: return launch_cfg<D, 8, 2, FT, VT, AT>(a, A);
-        case 16 * 8 + 2: return launch_cfg<D, 16, 2, FT, VT, AT>(a, A);
-        case 32 * 8 + 2: return launch_cfg<D, 32, 2, FT, VT, AT>(a, A);
-        case 64 * 8 + 2: return launch_cfg<D, 64, 2, FT, VT, AT>(a, A);
-        case 16 * 8 + 4: return launch_cfg<D, 16, 4, FT, VT, AT>(a, A);
-        case 64 * 8 + 4: return launch_cfg<D, 64, 4, FT, VT, AT>(a, A);
+    switch (G * 16 + CPL) {
+        case 4 * 16 + 4: return launch_cfg<D, 4, 4, FT, VT, AT>(a, A);
+        case 4 * 16 + 8: return launch_cfg<D, 4, 8, FT, VT, AT>(a, A);
+        case 8 * 16 + 1: return launch_cfg<D, 8, 1, FT, VT, AT>(a, A);
+        case 8 * 16 + 2: return launch_cfg<D, 8, 2, FT, VT, AT>(a, A);
+        case 8 * 16 + 4: return launch_cfg<D, 8, 4, FT, VT, AT>(a, A);
+        case 8 * 16 + 8: return launch_cfg<D, 8, 8, FT, VT, AT>(a, A);
+        case 16 * 16 + 1: return launch_cfg<D, 16, 1, FT, VT, AT>(a, A);
+        case 16 * 16 + 2: return launch_cfg<D, 16, 2, FT, VT, AT>(a, A);
+        case 16 * 16 + 4: return launch_cfg<D, 16, 4, FT, VT, AT>(a, A);
+        case 16 * 16 + 8: return launch_cfg<D, 16, 8, FT, VT, AT>(a, A);
+        case 32 * 16 + 1: return launch_cfg<D, 32, 1, FT, VT, AT>(a, A);
+        case 32 * 16 + 2: return launch_cfg<D, 32, 2, FT, VT, AT>(a, A);
+        case 64 * 16 + 1: return launch_cfg<D, 64, 1, FT, VT, AT>(a, A);
+        case 64 * 16 + 4: return launch_cfg<D, 64, 4, FT, VT, AT>(a, A);
         default: return SPT_EUNSUPPORTED;
     }
 }
