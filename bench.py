@@ -62,6 +62,125 @@ def read_counters():
         return None
 
 
+def _sampled_rel_errors(X, dev_outs, ref_factors, rows_per_mode=20, seed=0):
+    """Relative error of selected output rows (each mode's hottest row plus random rows)
+    against the FP64 oracle run on exactly the entries that feed them."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    errs = []
+    for n in range(X.d):
+        counts = np.bincount(X.subs[:, n], minlength=X.dims[n])
+        rows = np.unique(np.concatenate([[int(np.argmax(counts))],
+                                         rng.integers(0, X.dims[n], size=rows_per_mode)]))
+        mask = np.isin(X.subs[:, n], rows)
+        ref = oracle.mttkrp(X.subs[mask], X.vals[mask], X.dims, ref_factors, n)[rows]
+        got = dev_outs[n][rows].astype(np.float64)
+        errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    return max(errs)
+
+
+def bench_skewed4_bf16(spt, datagen, torch, dev, R=32, steps=5):
+    """BF16 vs FP32 factors on the 4-way skewed tensor, all modes, permuted kernel."""
+    t0 = time.time()
+    X = datagen.skewed4()
+    log(f"generated skewed4 ({X.nnz} entries) in {time.time() - t0:.1f}s")
+    T = spt.SparseTensor(torch.from_numpy(X.subs).to(dev), torch.from_numpy(X.vals).to(dev), X.dims)
+    T.validate()
+    T.permute()
+    A32 = [torch.from_numpy(a).to(dev) for a in datagen.factors(X.dims, R, seed=3, dtype=np.float32)]
+    A16 = [spt.to_bf16(a) for a in A32]
+    outs = [torch.empty((I, R), dtype=torch.float32, device=dev) for I in X.dims]
+    res = {}
+    for name, A in (("fp32", A32), ("bf16", A16)):
+        for n in range(X.d):
+            spt.mttkrp(T, A, n, out=outs[n])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            for n in range(X.d):
+                spt.mttkrp(T, A, n, out=outs[n])
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ref = [a.cpu().numpy().astype(np.float64) for a in A32]
+        err = _sampled_rel_errors(X, [o.cpu().numpy() for o in outs], ref)
+        sbytes = 2 if name == "bf16" else 4
+        gbs = X.nnz * model_bytes(X.d, R, s_f=sbytes) * X.d / (ms * 1e-3) / 1e9
+        res[name] = {"ms_all_modes": round(ms, 3), "model_gbs": round(gbs, 1),
+                     "max_rel_err_vs_fp64_oracle_sampled_rows": err}
+        log(f"skewed4 {name}: {ms:.3f} ms all modes, sampled rel err {err:.2e}")
+    res["bf16_speedup"] = round(res["fp32"]["ms_all_modes"] / res["bf16"]["ms_all_modes"], 3)
+    del T
+    return res
+
+
+def bench_batch64(spt, datagen, torch, dev, reps=10):
+    """64 uneven 3-way tensors x 3 modes: separate default launches vs separate tuned launches
+    vs one batched persistent kernel replayed from a HIP graph (tuned per product)."""
+    t0 = time.time()
+    Xs = datagen.batch64()
+    log(f"generated batch64 ({sum(x.nnz for x in Xs)} entries) in {time.time() - t0:.1f}s")
+    items = []
+    for t, X in enumerate(Xs):
+        T = spt.SparseTensor(torch.from_numpy(X.subs).to(dev), torch.from_numpy(X.vals).to(dev),
+                             X.dims)
+        T.permute()
+        R = X.meta["R"]
+        A = [torch.from_numpy(a).to(dev) for a in datagen.factors(X.dims, R, seed=400 + t,
+                                                                  dtype=np.float32)]
+        for n in range(3):
+            items.append({"X": T, "mode": n, "factors": A,
+                          "out": torch.empty((X.dims[n], R), dtype=torch.float32, device=dev),
+                          "nnz": X.nnz, "R": R})
+    torch.cuda.synchronize()
+
+    def run_separate(tuned):
+        for it in items:
+            kw = {}
+            if tuned:
+                kw = {k: it["tune"][k] for k in ("algo", "lanes", "cols", "chunk")}
+            spt.mttkrp(it["X"], it["factors"], it["mode"], out=it["out"], **kw)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    plain_ms = timed(lambda: run_separate(False))
+    t0 = time.time()
+    for it in items:
+        it["tune"] = spt.autotune(it["X"], it["factors"], it["mode"], batch=True, reps=2,
+                                  out=it["out"])
+    tune_s = time.time() - t0
+    tuned_ms = timed(lambda: run_separate(True))
+    B = spt.Batch([{k: it[k] for k in ("X", "mode", "factors", "out", "tune")} for it in items])
+    batch_ms = timed(B.launch)
+    model = sum(it["nnz"] * model_bytes(3, it["R"]) for it in items)
+    algos = {}
+    for it in items:
+        key = f"{it['tune']['algo']}:{it['tune']['lanes']}x{it['tune']['cols']}"
+        algos[key] = algos.get(key, 0) + 1
+    res = {"products": len(items), "entries_total": int(sum(x.nnz for x in Xs)),
+           "separate_default_ms": round(plain_ms, 3), "separate_tuned_ms": round(tuned_ms, 3),
+           "batched_graph_ms": round(batch_ms, 3),
+           "batched_speedup_vs_separate_default": round(plain_ms / batch_ms, 3),
+           "batched_speedup_vs_separate_tuned": round(tuned_ms / batch_ms, 3),
+           "batched_model_gbs": round(model / (batch_ms * 1e-3) / 1e9, 1),
+           "autotune_s": round(tune_s, 1), "tuned_layouts": algos}
+    log(f"batch64: separate {plain_ms:.3f} ms, tuned {tuned_ms:.3f} ms, batched {batch_ms:.3f} ms")
+    B.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +340,8 @@ def main():
         extras["pct_of_measured_stream"] = round(100.0 * main_res["gbs"] / triad_gbs, 1)
         del a, b, c
         log(f"triad {triad_gbs:.0f} GB/s")
+        extras["skewed4_bf16_vs_fp32"] = bench_skewed4_bf16(spt, datagen, torch, dev)
+        extras["batch64"] = bench_batch64(spt, datagen, torch, dev)
 
     # roofline of the dominant kernel (the permuted MTTKRP); per launch = one mode
     avg_launch_ms = float(np.mean(main_res["per_mode_ms"]))

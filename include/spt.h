@@ -56,9 +56,11 @@ typedef enum spt_algo {
     SPT_ALGO_PERMUTED = 2  /* mode-sorted traversal, wave segmented reduction */
 } spt_algo;
 
-/* Launch parameters of one MTTKRP.  Zero fields take the default.  The product
- * lanes_per_nnz * cols_per_lane must cover R (lanes_per_nnz in {8,16,32,64}, cols_per_lane in
- * {1,2,4}); nnz_per_wave is the number of entries one wavefront walks (a multiple of 64). */
+/* Launch parameters of one MTTKRP.  Zero fields take the default.  A lane group of
+ * lanes_per_nnz lanes evaluates one entry, each lane holding cols_per_lane consecutive rank
+ * columns; the product must cover R and cols_per_lane must divide R.  Compiled (lanes, cols)
+ * pairs: (4,4) (4,8) (8,1) (8,2) (8,4) (8,8) (16,1) (16,2) (16,4) (16,8) (32,1) (32,2) (64,1)
+ * (64,2) (64,4).  nnz_per_wave: entries one wavefront walks (a multiple of 64). */
 typedef struct spt_tune {
     int32_t algo;
     int32_t lanes_per_nnz;
@@ -120,7 +122,8 @@ int spt_tensor_destroy(spt_tensor *X);
  *   V(k, j) = lambda_j * sum_{i : l_in = k} x_i * prod_{m != n} A^(m)(l_im, j)
  *   X        tensor handle (SPT_ALGO_PERMUTED needs spt_tensor_permute(mode) first)
  *   mode     n, 0 <= n < d
- *   R        rank, 1 .. 256
+ *   R        rank: any value 1 .. 64; even values up to 128; multiples of 4 up to 256
+ *            (SPT_EUNSUPPORTED otherwise)
  *   factors  host array of d device pointers, A^(m) is I_m x R row-major of fdtype; the entry
  *            for m == n is not read and may be NULL; each matrix must be smaller than 4 GiB
  *            (SPT_EUNSUPPORTED otherwise: rows are addressed with 32-bit byte offsets)
@@ -140,6 +143,52 @@ int spt_mttkrp(const spt_tensor *X, int mode, int R, const void *const *factors,
 /* The launch parameters spt_mttkrp uses for (X, mode, R, fdtype, algo) when tune is NULL. */
 int spt_mttkrp_default_tune(const spt_tensor *X, int mode, int R, int fdtype, int algo,
                             spt_tune *out);
+
+/* The GPU vector size and factor block size the paper's register-array MTTKRP uses for rank R
+ * (Tab. sizes); the autotuner's candidate list contains the layout it maps to (lanes per entry =
+ * vector size, columns per lane = block size / vector size) whenever that layout is compiled. */
+int spt_paper_block_sizes(int R, int *vector_size, int *fbs);
+
+/* Autotuner: times every compiled launch configuration for (X, mode, R, fdtype) on `stream`
+ * (algorithm x lanes per entry x columns per lane x entries per wave; layouts that cover R with
+ * at most twice R lanes-columns) and returns the fastest in *best and its time per launch in
+ * *best_ms (host).  V is device scratch of the MTTKRP output size (overwritten).  reps: timed
+ * launches per candidate (0 = 3).  Synchronises `stream`. */
+enum {
+    SPT_TUNE_BATCH_CONFIGS = 1, /* only configurations the batched kernel supports */
+    SPT_TUNE_NO_ATOMIC = 2,
+    SPT_TUNE_NO_PERMUTED = 4
+};
+int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R, const void *const *factors,
+                        int fdtype, void *V, int flags, int reps, spt_tune *best, float *best_ms,
+                        void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched MTTKRP (beyond the paper): many (tensor, mode) products of uneven sizes in one
+ * persistent kernel.  Workgroups take units of 4 wave chunks from a global counter; each
+ * product keeps its own algorithm and lane layout.  The output zeroing and the kernel are
+ * captured once into a HIP graph that spt_batch_launch replays.
+ *   items i = 0..nitems-1: tensors[i] (3-way, F32 values), modes[i], ranks[i],
+ *            factors[i] (host array of d device factor pointers), outputs[i] (device
+ *            I_n x R floats), tunes[i] (from spt_mttkrp_autotune with SPT_TUNE_BATCH_CONFIGS,
+ *            or zeros for the default; must map to a configuration the batched kernel
+ *            supports, see spt_batch_supported_tune, else SPT_EUNSUPPORTED)
+ *   fdtype   SPT_F32 or SPT_BF16 for every item
+ *   ws       device workspace of spt_batch_workspace_bytes(nitems) (item table and counter);
+ *            caller-owned, must outlive the batch, as must every tensor, factor and output
+ * spt_batch_create synchronises `stream` once (item table upload) and captures on a stream of
+ * its own; spt_batch_launch enqueues one graph replay on `stream`.  Replays of one batch must
+ * not overlap (they share the work counter). */
+typedef struct spt_batch spt_batch;
+size_t spt_batch_workspace_bytes(int nitems);
+int spt_batch_supported_tune(int d, int fdtype, int algo, int lanes_per_nnz, int cols_per_lane);
+int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tensors,
+                     const int *modes, const int *ranks, const void *const *const *factors,
+                     int fdtype, void *const *outputs, const spt_tune *tunes, void *ws,
+                     size_t ws_bytes, void *stream);
+int spt_batch_launch(spt_batch *B, void *stream);
+int spt_batch_info(const spt_batch *B, int64_t *units, int *smem_bytes);
+int spt_batch_destroy(spt_batch *B);
 
 /* ---------------------------------------------------------------------------------------------
  * CP-ALS (Sec. 3 uses alternating least squares and defers the algorithm to Kolda & Bader).

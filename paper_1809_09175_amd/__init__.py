@@ -14,7 +14,8 @@ from ._lib import (ALGO_ATOMIC, ALGO_AUTO, ALGO_PERMUTED, SPT_BF16, SPT_F32, SPT
                    SptTune, SptUnavailable)
 
 __all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPPoissonLoss",
-           "default_tune", "to_bf16", "stream_triad", "SptError", "SptUnavailable",
+           "default_tune", "autotune", "Batch", "to_bf16", "stream_triad", "SptError",
+           "SptUnavailable",
            "ALGO_AUTO", "ALGO_ATOMIC", "ALGO_PERMUTED", "dtype_code"]
 
 _ALGOS = {"auto": ALGO_AUTO, "atomic": ALGO_ATOMIC, "permuted": ALGO_PERMUTED,
@@ -327,3 +328,84 @@ class GCPPoissonLoss(torch.autograd.Function):
             ctypes.c_void_p(y.data_ptr()), _lib.ptr_array([t.data_ptr() for t in grads]), None,
             _stream()), "spt_gcp_poisson_backward")
         return (None, None, *grads)
+
+
+# ------------------------------------------------------------------ autotuner and batching
+
+def autotune(X: SparseTensor, factors, mode: int, batch=False, algos=("atomic", "permuted"),
+             reps=3, out=None, stream=None):
+    """Time every compiled launch configuration of this MTTKRP on the device; returns the
+    fastest as a dict(algo, lanes, cols, chunk, ms)."""
+    lib = _lib.load()
+    ref = factors[0] if factors[0] is not None else factors[1]
+    R = int(ref.shape[1])
+    fd = dtype_code(ref)
+    if out is None:
+        out = torch.empty((X.dims[mode], R), dtype=torch.float64 if fd == SPT_F64 else torch.float32,
+                          device=X.device)
+    flags = (_lib.TUNE_BATCH_CONFIGS if batch else 0)
+    if "atomic" not in algos:
+        flags |= _lib.TUNE_NO_ATOMIC
+    if "permuted" not in algos:
+        flags |= _lib.TUNE_NO_PERMUTED
+    best = SptTune()
+    ms = ctypes.c_float()
+    _lib.check(lib.spt_mttkrp_autotune(X.handle, int(mode), R, _factor_ptrs(factors, mode), fd,
+                                       ctypes.c_void_p(out.data_ptr()), flags, int(reps),
+                                       ctypes.byref(best), ctypes.byref(ms), _stream(stream)),
+               "spt_mttkrp_autotune")
+    return {"algo": ["auto", "atomic", "permuted"][best.algo], "lanes": best.lanes_per_nnz,
+            "cols": best.cols_per_lane, "chunk": best.nnz_per_wave, "ms": ms.value}
+
+
+class Batch:
+    """Many MTTKRPs in one persistent kernel replayed from a HIP graph.
+
+    items: list of dicts with keys X (SparseTensor), mode, factors, out (float32 CUDA tensor),
+    and optional tune (dict as returned by autotune(batch=True))."""
+
+    def __init__(self, items, stream=None):
+        lib = _lib.load()
+        n = len(items)
+        self.items = items
+        fd = dtype_code(items[0]["factors"][0])
+        self._factor_arrays = [_factor_ptrs(it["factors"]) for it in items]
+        tensors = (ctypes.c_void_p * n)(*[it["X"].handle.value for it in items])
+        modes = (ctypes.c_int * n)(*[int(it["mode"]) for it in items])
+        ranks = (ctypes.c_int * n)(*[int(it["factors"][0].shape[1]) for it in items])
+        facs = (ctypes.c_void_p * n)(*[ctypes.cast(a, ctypes.c_void_p).value
+                                       for a in self._factor_arrays])
+        outs = (ctypes.c_void_p * n)(*[it["out"].data_ptr() for it in items])
+        tunes = (SptTune * n)()
+        for i, it in enumerate(items):
+            t = it.get("tune") or {}
+            tunes[i] = _tune(t.get("algo", "auto"), t.get("lanes", 0), t.get("cols", 0),
+                             t.get("chunk", 0))
+        nbytes = lib.spt_batch_workspace_bytes(n)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=items[0]["out"].device)
+        h = ctypes.c_void_p()
+        _lib.check(lib.spt_batch_create(ctypes.byref(h), n, tensors, modes, ranks, facs, fd, outs,
+                                        tunes, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                        _stream(stream)), "spt_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().spt_batch_launch(self._h, _stream(stream)), "spt_batch_launch")
+
+    def info(self):
+        u = ctypes.c_int64()
+        sm = ctypes.c_int()
+        _lib.check(_lib.load().spt_batch_info(self._h, ctypes.byref(u), ctypes.byref(sm)),
+                   "spt_batch_info")
+        return {"units": u.value, "smem": sm.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().spt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

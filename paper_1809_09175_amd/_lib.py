@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libspt.so")
 SPT_OK, SPT_EINVAL, SPT_ERANGE, SPT_EHIP, SPT_ESINGULAR = 0, -1, -2, -3, -4
 SPT_EWORKSPACE, SPT_EUNSUPPORTED, SPT_ESTATE = -5, -6, -7
 SPT_F64, SPT_F32, SPT_BF16 = 0, 1, 2
+TUNE_BATCH_CONFIGS, TUNE_NO_ATOMIC, TUNE_NO_PERMUTED = 1, 2, 4
 ALGO_AUTO, ALGO_ATOMIC, ALGO_PERMUTED = 0, 1, 2
 
 _c_p = ctypes.c_void_p
@@ -52,6 +53,16 @@ SIGNATURES = {
                                        _c_p]),
     "spt_gcp_poisson_backward": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p,
                                         _c_p, _c_p]),
+    "spt_paper_block_sizes": (_c_i, [_c_i, _c_p, _c_p]),
+    "spt_mttkrp_autotune": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_i, _c_p, _c_i, _c_i, _c_p, _c_p,
+                                   _c_p]),
+    "spt_batch_workspace_bytes": (_c_sz, [_c_i]),
+    "spt_batch_supported_tune": (_c_i, [_c_i, _c_i, _c_i, _c_i, _c_i]),
+    "spt_batch_create": (_c_i, [_c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_i, _c_p, _c_p, _c_p,
+                                _c_sz, _c_p]),
+    "spt_batch_launch": (_c_i, [_c_p, _c_p]),
+    "spt_batch_info": (_c_i, [_c_p, _c_p, _c_p]),
+    "spt_batch_destroy": (_c_i, [_c_p]),
     "spt_f32_to_bf16": (_c_i, [_c_p, _c_p, _c_i64, _c_p]),
     "spt_stream_triad": (_c_i, [_c_p, _c_p, _c_p, ctypes.c_float, _c_i64, _c_p]),
 }

@@ -31,7 +31,7 @@ static bool cfg_supported(int G, int CPL) {
         case 8 * 16 + 1: case 8 * 16 + 2: case 8 * 16 + 4: case 8 * 16 + 8:
         case 16 * 16 + 1: case 16 * 16 + 2: case 16 * 16 + 4: case 16 * 16 + 8:
         case 32 * 16 + 1: case 32 * 16 + 2:
-        case 64 * 16 + 1: case 64 * 16 + 4:
+        case 64 * 16 + 1: case 64 * 16 + 2: case 64 * 16 + 4:
             return true;
         default:
             return false;
@@ -55,31 +55,70 @@ static int default_hbits(int R, int G, int CPL, int fdtype, int rq) {
     return hb;
 }
 
+// Default lane layout, from measurements on MI355X (1e8-entry Zipf tensor, R = 16/32/64): the
+// permuted kernel is fastest with few lanes per entry and wide per-lane loads (8 lanes x 2/4/8
+// FP32 columns), the atomic kernel with one column per lane (its LDS and global atomics are
+// per column either way).  Columns per lane must divide R.
+static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out) {
+    int cpl = 1, G = 8;
+    if (algo == SPT_ALGO_PERMUTED) {
+        const int min_lanes = (fdtype == SPT_BF16) ? 4 : 8;
+        const int opts[] = {8, 4, 2, 1};
+        for (int c : opts) {
+            if (R % c != 0 || R / c < min_lanes) continue;
+            const int g = pow2_at_least(R / c);
+            if (cfg_supported(g, c)) {
+                cpl = c;
+                G = g;
+                *G_out = G;
+                *cpl_out = cpl;
+                return;
+            }
+        }
+    } else if (R <= 16 && R % 2 == 0 && R >= 8) {
+        *G_out = 8;
+        *cpl_out = 2;
+        return;
+    }
+    // one column per lane up to 64 columns, then wider lanes (R must then be even, and a
+    // multiple of 4 above 128; other ranks are rejected by resolve_tune)
+    if (R <= 64) {
+        cpl = 1;
+        G = pow2_at_least(R);
+        if (G < 8) G = 8;
+    } else if (R <= 128 && R % 8 == 0) {
+        cpl = 8;
+        G = 16;
+    } else if (R <= 128) {
+        cpl = 2;
+        G = 64;
+    } else {
+        cpl = 4;
+        G = 64;
+    }
+    *G_out = G;
+    *cpl_out = cpl;
+}
+
 int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tune *in,
                  spt_tune *out) {
     spt_tune t = in ? *in : spt_tune{0, 0, 0, 0};
     if (t.algo == SPT_ALGO_AUTO) t.algo = X->permuted[mode] ? SPT_ALGO_PERMUTED : SPT_ALGO_ATOMIC;
     if (t.algo != SPT_ALGO_ATOMIC && t.algo != SPT_ALGO_PERMUTED) return SPT_EINVAL;
-    int cpl = t.cols_per_lane;
-    if (cpl == 0) {
-        if (fdtype == SPT_BF16 && R % 2 == 0 && R <= 128) cpl = 2;
-        else if (R <= 64) cpl = 1;
-        else if (R <= 128) cpl = 2;
-        else cpl = 4;
-        if (cpl == 4 && R % 4 != 0) cpl = 2;
-        if (cpl == 2 && R % 2 != 0) cpl = 1;
+    int G = t.lanes_per_nnz, cpl = t.cols_per_lane;
+    if (G == 0 && cpl == 0) {
+        default_layout(R, fdtype, t.algo, &G, &cpl);
+    } else if (cpl == 0) {
+        cpl = (R + G - 1) / G;
+        while (cpl & (cpl - 1)) ++cpl;
+    } else if (G == 0) {
+        G = pow2_at_least((R + cpl - 1) / cpl);
+        if (G < 4) G = 4;
     }
     if (cpl != 1 && cpl != 2 && cpl != 4 && cpl != 8) return SPT_EINVAL;
     if (R % cpl != 0) return SPT_EUNSUPPORTED;
-    int G = t.lanes_per_nnz;
-    if (G == 0) {
-        G = pow2_at_least((R + cpl - 1) / cpl);
-        if (G < 8) G = 8;
-        if (cpl == 4 && G < 64 && G > 16) G = 64;
-        if (cpl == 4 && G < 16) G = 16;
-    }
     if (G * cpl < R || !cfg_supported(G, cpl)) return SPT_EUNSUPPORTED;
-    if (t.nnz_per_wave == 0) t.nnz_per_wave = 2048;
+    if (t.nnz_per_wave == 0) t.nnz_per_wave = (t.algo == SPT_ALGO_PERMUTED) ? 4096 : 2048;
     if (t.nnz_per_wave < 64 || t.nnz_per_wave % 64 != 0 || t.nnz_per_wave > (1 << 20))
         return SPT_EINVAL;
     t.lanes_per_nnz = G;
@@ -170,4 +209,91 @@ extern "C" int spt_mttkrp_default_tune(const spt_tensor *X, int mode, int R, int
         return SPT_EINVAL;
     spt_tune in{algo, 0, 0, 0};
     return resolve_tune(X, mode, R, fdtype, &in, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// autotuner: time every candidate launch configuration on the device and keep the fastest
+// ------------------------------------------------------------------------------------------
+
+extern "C" int spt_batch_supported_tune(int d, int fdtype, int algo, int lanes_per_nnz,
+                                        int cols_per_lane);
+
+extern "C" int spt_paper_block_sizes(int R, int *vector_size, int *fbs) {
+    // GPU vector and factor block sizes by rank for the register-array MTTKRP (Tab. sizes)
+    static const int lo[] = {1, 2, 3, 4, 5, 8, 9, 17, 25, 48, 49, 96, 97};
+    static const int vs[] = {1, 2, 2, 4, 4, 8, 8, 8, 8, 16, 16, 32, 32};
+    static const int fb[] = {1, 2, 4, 4, 8, 8, 16, 24, 32, 48, 64, 96, 128};
+    if (R < 1 || vector_size == nullptr || fbs == nullptr) return SPT_EINVAL;
+    int k = 0;
+    for (int i = 0; i < 13; ++i)
+        if (R >= lo[i]) k = i;
+    *vector_size = vs[k];
+    *fbs = fb[k];
+    return SPT_OK;
+}
+
+extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
+                                   const void *const *factors, int fdtype, void *V, int flags,
+                                   int reps, spt_tune *best, float *best_ms, void *stream) {
+    int rc = check_mttkrp_args(X, mode, R, factors, fdtype, V);
+    if (rc) return rc;
+    if (best == nullptr) return SPT_EINVAL;
+    if (reps < 1) reps = 3;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    static const int cfgs[][2] = {{4, 4},  {4, 8},  {8, 1},  {8, 2},  {8, 4},
+                                  {8, 8},  {16, 1}, {16, 2}, {16, 4}, {16, 8},
+                                  {32, 1}, {32, 2}, {64, 1}, {64, 2}, {64, 4}};
+    static const int chunks[] = {512, 1024, 2048, 4096};
+    const bool batch_only = (flags & SPT_TUNE_BATCH_CONFIGS) != 0;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SPT_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return SPT_EHIP;
+    }
+    float bms = 1e30f;
+    spt_tune bt{0, 0, 0, 0};
+    int tried = 0;
+    rc = SPT_OK;
+    for (int algo = SPT_ALGO_ATOMIC; algo <= SPT_ALGO_PERMUTED && rc == SPT_OK; ++algo) {
+        if (algo == SPT_ALGO_PERMUTED && (!X->permuted[mode] || (flags & SPT_TUNE_NO_PERMUTED)))
+            continue;
+        if (algo == SPT_ALGO_ATOMIC && (flags & SPT_TUNE_NO_ATOMIC)) continue;
+        for (const auto &c : cfgs) {
+            const int G = c[0], CPL = c[1];
+            // lanes must cover R; skip layouts that leave more than half the lanes idle
+            if (G * CPL < R || R % CPL != 0) continue;
+            if (G * CPL >= 2 * R && G * CPL > 16) continue;
+            if (batch_only && !spt_batch_supported_tune(X->d, fdtype, algo, G, CPL)) continue;
+            for (int chunk : chunks) {
+                spt_tune t{algo, G, CPL, chunk}, r;
+                if (resolve_tune(X, mode, R, fdtype, &t, &r) != SPT_OK) continue;
+                rc = launch_mttkrp(X, mode, R, factors, fdtype, nullptr, nullptr, V, r, s);
+                if (rc) break;
+                hipEventRecord(e0, s);
+                for (int k = 0; k < reps && rc == SPT_OK; ++k)
+                    rc = launch_mttkrp(X, mode, R, factors, fdtype, nullptr, nullptr, V, r, s);
+                hipEventRecord(e1, s);
+                if (rc || hipEventSynchronize(e1) != hipSuccess) {
+                    rc = rc ? rc : SPT_EHIP;
+                    break;
+                }
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                ms /= reps;
+                ++tried;
+                if (ms < bms) {
+                    bms = ms;
+                    bt = r;
+                }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    if (tried == 0) return SPT_EUNSUPPORTED;
+    *best = bt;
+    if (best_ms) *best_ms = bms;
+    return SPT_OK;
 }

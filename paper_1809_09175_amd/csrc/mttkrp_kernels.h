@@ -182,25 +182,33 @@ struct UnrollFor {
     static constexpr int value = raw < G ? raw : G;
 };
 
+// LDS of one wavefront in the permuted kernel: the staged records of the current batch and the
+// boundary partial rows (first and last row of every lane group's slice).
+template <int D, int G, int CPL, class VT, class AT>
+struct PermShared {
+    static constexpr int RQ = RecShape<D, VT>::RQ, NG = kWave / G;
+    int4 rec[kWave * RQ];
+    AT part[2 * NG][G * CPL];
+    int pkey[2 * NG];
+};
+
+// One wavefront processes sorted positions [c0, min(c0 + chunk, P)) of mode n (c0 < P).
 template <int D, int G, int CPL, class FT, class VT, class AT>
-__global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
-    const int4 *__restrict__ rec, const int32_t *__restrict__ perm, int64_t P, int n, int R,
-    FactorSet<FT> A, const double *__restrict__ lambda, const VT *__restrict__ vovr,
-    AT *__restrict__ V, int chunk) {
+__device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &sm,
+                                                const int4 *__restrict__ rec,
+                                                const int32_t *__restrict__ perm, int64_t P,
+                                                int n, int R, const FactorSet<FT> &A,
+                                                const double *__restrict__ lambda,
+                                                const VT *__restrict__ vovr, AT *__restrict__ V,
+                                                int chunk, int64_t c0) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int NG = kWave / G;
     constexpr int U = UnrollFor<CPL, G>::value;
-    __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
-    __shared__ AT s_part[kBlock / kWave][2 * NG][G * CPL];
-    __shared__ int s_pkey[kBlock / kWave][2 * NG];
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
     const bool colok = col0 < R;
     const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
-    const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
-    if (c0 >= P) return;  // whole wavefront leaves together
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
     const int S = chunk / NG;  // slice per group
     const int64_t gb = c0 + (int64_t)g * S;
@@ -215,8 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
     for (int c = 0; c < CPL; ++c)
         lam[c] = (lambda != nullptr && colok) ? (AT)lambda[col0 + c] : (AT)1;
     if (gl == 0) {
-        s_pkey[wave][2 * g] = -1;
-        s_pkey[wave][2 * g + 1] = -1;
+        sm.pkey[2 * g] = -1;
+        sm.pkey[2 * g + 1] = -1;
     }
 
     // software pipeline: the records of batch b+1 and the permutation entries of batch b+2
@@ -239,10 +247,10 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
 
     for (int b = 0; b < nb; ++b) {
         if (b * G + gl < glen) {
-            s_rec[wave][lane * RQ] = rc0;
-            if constexpr (RQ == 2) s_rec[wave][lane * RQ + 1] = rc1;
+            sm.rec[lane * RQ] = rc0;
+            if constexpr (RQ == 2) sm.rec[lane * RQ + 1] = rc1;
             if (vovr != nullptr)
-                rec_set_value<VT, RW>(reinterpret_cast<int *>(&s_rec[wave][lane * RQ]), vo);
+                rec_set_value<VT, RW>(reinterpret_cast<int *>(&sm.rec[lane * RQ]), vo);
         }
         wave_sync();
         if (pn >= 0) {
@@ -253,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
         pn = ((b + 2) * G + gl < glen) ? gperm[(b + 2) * G + gl] : -1;
 
         const int cnt = glen - b * G < G ? glen - b * G : G;
-        const int4 *sr = &s_rec[wave][g * G * RQ];
+        const int4 *sr = &sm.rec[g * G * RQ];
         for (int s0 = 0; s0 < cnt; s0 += U) {
             AT t[U][CPL];
             int kk[U];
@@ -284,8 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
                         if (key >= 0) {
                             if (key == first_key) {
 #pragma unroll
-                                for (int c = 0; c < CPL; ++c) s_part[wave][2 * g][col0 + c] = acc[c];
-                                if (gl == 0) s_pkey[wave][2 * g] = key;
+                                for (int c = 0; c < CPL; ++c) sm.part[2 * g][col0 + c] = acc[c];
+                                if (gl == 0) sm.pkey[2 * g] = key;
                             } else if (colok) {
                                 store_cols<AT, CPL>(V + (int64_t)key * R + col0, acc);
                             }
@@ -305,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
     }
     if (key >= 0) {
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) s_part[wave][2 * g + 1][col0 + c] = acc[c];
-        if (gl == 0) s_pkey[wave][2 * g + 1] = key;
+        for (int c = 0; c < CPL; ++c) sm.part[2 * g + 1][col0 + c] = acc[c];
+        if (gl == 0) sm.pkey[2 * g + 1] = key;
     }
     wave_sync();
     if (g == 0) {
@@ -316,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
 #pragma unroll
         for (int c = 0; c < CPL; ++c) cacc[c] = 0;
         for (int e = 0; e < 2 * NG; ++e) {
-            const int ke = s_pkey[wave][e];
+            const int ke = sm.pkey[e];
             if (ke < 0) continue;
             if (ke != ck) {
                 if (ck >= 0 && colok) {
@@ -329,23 +337,36 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
                 for (int c = 0; c < CPL; ++c) cacc[c] = 0;
             }
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) cacc[c] += s_part[wave][e][col0 + c];
+            for (int c = 0; c < CPL; ++c) cacc[c] += sm.part[e][col0 + c];
         }
         if (ck >= 0 && colok) atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
     }
 }
 
 template <int D, int G, int CPL, class FT, class VT, class AT>
-__global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
-    const int4 *__restrict__ rec, int64_t P, int n, int R, FactorSet<FT> A,
-    const double *__restrict__ lambda, const VT *__restrict__ vovr, AT *__restrict__ V,
-    int chunk, int hbits) {
+__global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
+    const int4 *__restrict__ rec, const int32_t *__restrict__ perm, int64_t P, int n, int R,
+    FactorSet<FT> A, const double *__restrict__ lambda, const VT *__restrict__ vovr,
+    AT *__restrict__ V, int chunk) {
+    __shared__ PermShared<D, G, CPL, VT, AT> sm[kBlock / kWave];
+    const int wave = threadIdx.x >> 6;
+    const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
+    if (c0 >= P) return;  // whole wavefront leaves together
+    perm_wave_chunk<D, G, CPL, FT, VT, AT>(sm[wave], rec, perm, P, n, R, A, lambda, vovr, V, chunk, c0);
+}
+
+// One workgroup processes storage positions [bc0, bc0 + 4 chunk) (one chunk per wavefront)
+// through the LDS table in smem4.  Every thread of the workgroup must call it.
+template <int D, int G, int CPL, class FT, class VT, class AT>
+__device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__restrict__ rec,
+                                                  int64_t P, int n, int R, const FactorSet<FT> &A,
+                                                  const double *__restrict__ lambda,
+                                                  const VT *__restrict__ vovr,
+                                                  AT *__restrict__ V, int chunk, int hbits,
+                                                  int64_t bc0) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
-    constexpr int NG = kWave / G;
     constexpr int RP = G * CPL;
     constexpr int U = UnrollFor<CPL, G>::value;
-    (void)NG;
-    extern __shared__ int4 smem4[];
     int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
     int *hkeys = reinterpret_cast<int *>(smem4 + (kBlock / kWave) * kWave * RQ);
     const int H = hbits > 0 ? (1 << hbits) : 0;
@@ -365,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
     for (int c = 0; c < CPL; ++c)
         lam[c] = (lambda != nullptr && colok) ? (AT)lambda[col0 + c] : (AT)1;
 
-    const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
+    const int64_t c0 = bc0 + (int64_t)wave * chunk;
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
     const int len = c1 > c0 ? (int)(c1 - c0) : 0;
     const int nb = (len + kWave - 1) / kWave;
@@ -439,6 +460,16 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
     }
 }
 
+template <int D, int G, int CPL, class FT, class VT, class AT>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
+    const int4 *__restrict__ rec, int64_t P, int n, int R, FactorSet<FT> A,
+    const double *__restrict__ lambda, const VT *__restrict__ vovr, AT *__restrict__ V,
+    int chunk, int hbits) {
+    extern __shared__ int4 smem4[];
+    atomic_block_unit<D, G, CPL, FT, VT, AT>(smem4, rec, P, n, R, A, lambda, vovr, V, chunk, hbits,
+                                             (int64_t)blockIdx.x * (kBlock / kWave) * chunk);
+}
+
 // ------------------------------------------------------------------------------------------
 // launch dispatch over (order, lane config) for one dtype triple
 // ------------------------------------------------------------------------------------------
@@ -499,6 +530,7 @@ int launch_d(const MttkrpArgs &a, const FactorSet<FT> &A, int G, int CPL) {
         case 32 * 16 + 1: return launch_cfg<D, 32, 1, FT, VT, AT>(a, A);
         case 32 * 16 + 2: return launch_cfg<D, 32, 2, FT, VT, AT>(a, A);
         case 64 * 16 + 1: return launch_cfg<D, 64, 1, FT, VT, AT>(a, A);
+        case 64 * 16 + 2: return launch_cfg<D, 64, 2, FT, VT, AT>(a, A);
         case 64 * 16 + 4: return launch_cfg<D, 64, 4, FT, VT, AT>(a, A);
         default: return SPT_EUNSUPPORTED;
     }

@@ -70,3 +70,35 @@ def test_workspace_accounting_matches_section5_storage():
     perms_and_keys = 2 * 3 * 4 * P
     sort_scratch = 2 * 4 * P
     assert records + perms_and_keys + sort_scratch <= ws < records + perms_and_keys + sort_scratch + (8 << 20)
+
+
+def test_paper_block_size_table_matches_golden():
+    """spt_paper_block_sizes reproduces Tab. sizes (tests/golden/paper_tab_sizes.txt)."""
+    from paper_1809_09175_amd import _lib
+    lib = _lib.load()
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_tab_sizes.txt")):
+        if line.strip() and not line.startswith("#"):
+            rows.append(tuple(int(x) for x in line.split()))
+    for lo, hi, vs, fbs in rows:
+        for R in range(lo, (hi or lo + 200) + 1):
+            v = ctypes.c_int()
+            f = ctypes.c_int()
+            assert lib.spt_paper_block_sizes(R, ctypes.byref(v), ctypes.byref(f)) == 0
+            assert (v.value, f.value) == (vs, fbs), R
+    # at most four columns per thread, as the paper states for its choices
+    for R in range(1, 300):
+        v = ctypes.c_int()
+        f = ctypes.c_int()
+        lib.spt_paper_block_sizes(R, ctypes.byref(v), ctypes.byref(f))
+        assert f.value <= 4 * v.value
+
+
+def test_batch_config_queries():
+    from paper_1809_09175_amd import _lib
+    lib = _lib.load()
+    assert lib.spt_batch_workspace_bytes(0) == 0
+    assert lib.spt_batch_workspace_bytes(64) >= 64 * 64
+    assert lib.spt_batch_supported_tune(3, 1, 2, 8, 4) == 1      # F32, permuted, 8 x 4
+    assert lib.spt_batch_supported_tune(3, 0, 2, 8, 4) == 0      # F64 not batched
+    assert lib.spt_batch_supported_tune(4, 1, 2, 8, 4) == 0      # 3-way only

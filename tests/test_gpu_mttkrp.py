@@ -98,6 +98,7 @@ CASES = [
     ("f32", (40, 30, 20, 10, 5), 30_000, (1.1, 0.0, 0.0, 0.0, 0.0), 24),
     ("f32", (300, 200), 10_000, (1.1, 1.1), 48),
     ("f32", (1000, 1000, 1000), 60_000, (1.1, 1.1, 1.1), 128),
+    ("f32", (1000, 1000, 1000), 30_000, (1.1, 1.1, 1.1), 98),
     ("f32", (200, 150, 100), 30_000, (1.1, 1.1, 1.1), 256),
     ("f64", (100, 80, 60), 10_000, (0.0, 0.0, 0.0), 16),
     ("f64", (500, 400, 30), 50_000, (1.1, 1.1, 1.1), 32),
@@ -132,7 +133,7 @@ def test_mttkrp_parity(gpu, case, algo):
 def _configs_for(R, kind):
     out = []
     for lanes, cols in [(4, 4), (4, 8), (8, 1), (8, 2), (8, 4), (8, 8), (16, 1), (16, 2),
-                        (16, 4), (16, 8), (32, 1), (32, 2), (64, 1), (64, 4)]:
+                        (16, 4), (16, 8), (32, 1), (32, 2), (64, 1), (64, 2), (64, 4)]:
         if lanes * cols >= R and R % cols == 0:
             out.append((lanes, cols))
     return out
