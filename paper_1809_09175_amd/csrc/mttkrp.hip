@@ -118,7 +118,13 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
     if (cpl != 1 && cpl != 2 && cpl != 4 && cpl != 8) return SPT_EINVAL;
     if (R % cpl != 0) return SPT_EUNSUPPORTED;
     if (G * cpl < R || !cfg_supported(G, cpl)) return SPT_EUNSUPPORTED;
-    if (t.nnz_per_wave == 0) t.nnz_per_wave = (t.algo == SPT_ALGO_PERMUTED) ? 4096 : 2048;
+    if (t.nnz_per_wave == 0) {
+        // long chunks amortise the chunk-boundary work, but a small tensor needs enough
+        // wavefronts to occupy the GPU: aim for at least ~2048 wave chunks
+        const int64_t cap = (t.algo == SPT_ALGO_PERMUTED) ? 4096 : 2048;
+        int64_t c = (X->P / 2048) & ~int64_t(63);
+        t.nnz_per_wave = (int)(c < 256 ? 256 : (c > cap ? cap : c));
+    }
     if (t.nnz_per_wave < 64 || t.nnz_per_wave % 64 != 0 || t.nnz_per_wave > (1 << 20))
         return SPT_EINVAL;
     t.lanes_per_nnz = G;
