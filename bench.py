@@ -87,6 +87,7 @@ def bench_skewed4_bf16(spt, datagen, torch, dev, R=32, steps=5):
     T = spt.SparseTensor(torch.from_numpy(X.subs).to(dev), torch.from_numpy(X.vals).to(dev), X.dims)
     T.validate()
     T.permute()
+    T.sort_copy()
     A32 = [torch.from_numpy(a).to(dev) for a in datagen.factors(X.dims, R, seed=3, dtype=np.float32)]
     A16 = [spt.to_bf16(a) for a in A32]
     outs = [torch.empty((I, R), dtype=torch.float32, device=dev) for I in X.dims]
@@ -127,6 +128,7 @@ def bench_batch64(spt, datagen, torch, dev, reps=10):
         T = spt.SparseTensor(torch.from_numpy(X.subs).to(dev), torch.from_numpy(X.vals).to(dev),
                              X.dims)
         T.permute()
+        T.sort_copy()
         R = X.meta["R"]
         A = [torch.from_numpy(a).to(dev) for a in datagen.factors(X.dims, R, seed=400 + t,
                                                                   dtype=np.float32)]
@@ -276,6 +278,11 @@ def main():
                 "wall_s": wall}
 
     R = args.rank
+    # mode-sorted record copies: built once, like the permutations
+    T.sort_copy()
+    torch.cuda.synchronize()
+    copy_ms = timed(lambda: T.sort_copy())
+    log(f"sorted record copies, all modes: {copy_ms:.2f} ms")
     if args.profile:
         args.steps, args.warmup, args.quick, args.no_cpu = 2, 1, True, True
         n = 1 << 28
@@ -285,8 +292,10 @@ def main():
         spt.stream_triad(a, b, c)
         torch.cuda.synchronize()
         del a, b, c
-    main_res = measure(R, "permuted", args.steps, args.warmup)
-    log(f"R={R} permuted: {main_res['ms_per_step']:.3f} ms/step, {main_res['gbs']:.0f} GB/s")
+    main_res = measure(R, "permuted_copy", args.steps, args.warmup)
+    log(f"R={R} permuted (sorted copies): {main_res['ms_per_step']:.3f} ms/step, {main_res['gbs']:.0f} GB/s")
+    gather_res = measure(R, "permuted", max(2, args.steps // 2), 1 if args.profile else 2)
+    log(f"R={R} permuted (gather): {gather_res['ms_per_step']:.3f} ms/step, {gather_res['gbs']:.0f} GB/s")
     atomic_res = measure(R, "atomic", max(2, args.steps // 2), 1 if args.profile else 2)
     log(f"R={R} atomic:   {atomic_res['ms_per_step']:.3f} ms/step, {atomic_res['gbs']:.0f} GB/s")
 
@@ -295,21 +304,26 @@ def main():
     if not args.quick:
         for r in (16, 32, 64):
             if r == R:
-                per_rank[str(r)] = {"permuted_gbs": round(main_res["gbs"], 1),
+                per_rank[str(r)] = {"permuted_copy_gbs": round(main_res["gbs"], 1),
+                                    "permuted_gbs": round(gather_res["gbs"], 1),
                                     "atomic_gbs": round(atomic_res["gbs"], 1),
-                                    "permuted_ms": round(main_res["ms_per_step"], 3),
+                                    "permuted_copy_ms": round(main_res["ms_per_step"], 3),
+                                    "permuted_ms": round(gather_res["ms_per_step"], 3),
                                     "atomic_ms": round(atomic_res["ms_per_step"], 3)}
                 continue
+            pc = measure(r, "permuted_copy", 5, 1)
             p = measure(r, "permuted", 5, 1)
             a = measure(r, "atomic", 3, 1)
-            per_rank[str(r)] = {"permuted_gbs": round(p["gbs"], 1), "atomic_gbs": round(a["gbs"], 1),
+            per_rank[str(r)] = {"permuted_copy_gbs": round(pc["gbs"], 1),
+                                "permuted_gbs": round(p["gbs"], 1), "atomic_gbs": round(a["gbs"], 1),
+                                "permuted_copy_ms": round(pc["ms_per_step"], 3),
                                 "permuted_ms": round(p["ms_per_step"], 3),
                                 "atomic_ms": round(a["ms_per_step"], 3)}
-            log(f"R={r}: permuted {p['gbs']:.0f} GB/s, atomic {a['gbs']:.0f} GB/s")
+            log(f"R={r}: permuted copy {pc['gbs']:.0f}, gather {p['gbs']:.0f}, atomic {a['gbs']:.0f} GB/s")
         # BF16 factors on the same tensor
         A32 = factors_for(R)
         A16 = [spt.to_bf16(a) for a in A32]
-        b16 = measure(R, "permuted", 5, 1, A=A16)
+        b16 = measure(R, "permuted_copy", 5, 1, A=A16)
         extras["bf16_factors_same_tensor"] = {
             "ms_per_step": round(b16["ms_per_step"], 3),
             "speedup_vs_fp32": round(main_res["ms_per_step"] / b16["ms_per_step"], 3)}
@@ -325,7 +339,9 @@ def main():
         extras["cp_als_sweep_ms"] = round(sweep_ms, 3)
         extras["cp_fit_ms"] = round(fit_ms, 3)
         extras["sort_ms_all_modes"] = round(sort_ms, 3)
+        extras["sorted_copy_ms_all_modes"] = round(copy_ms, 3)
         extras["sort_over_cp_als_iteration"] = round(sort_ms / (sweep_ms + fit_ms), 3)
+        extras["sort_and_copy_over_cp_als_iteration"] = round((sort_ms + copy_ms) / (sweep_ms + fit_ms), 3)
         log(f"CP-ALS sweep {sweep_ms:.2f} ms, fit {fit_ms:.2f} ms")
         del st
         # STREAM-style triad on 3 x 1 GiB
@@ -344,13 +360,15 @@ def main():
         extras["batch64"] = bench_batch64(spt, datagen, torch, dev)
 
     # roofline of the dominant kernel (the permuted MTTKRP); per launch = one mode
+    dtune = spt.default_tune(T, 0, R, torch.float32, algo="permuted_copy")
     avg_launch_ms = float(np.mean(main_res["per_mode_ms"]))
     per_launch_bytes = P * model_bytes(d, R)
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     traffic = read_counters()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_mttkrp_perm<3,32,1,float>",
+                "traffic": traffic,
+                "kernel": "k_mttkrp_perm<3," + str(dtune["lanes"]) + "," + str(dtune["cols"]) + ",float> (sorted record copies)",
                 "per_launch_model_bytes": per_launch_bytes,
                 "avg_launch_ms": round(avg_launch_ms, 4)}
 
@@ -385,11 +403,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "powerlaw3: 3-way 500000x500000x20000, 1e8 entries, Zipf(1.1) "
                                "per mode, FP32 values and factors, all-mode MTTKRP",
-                   "rank": R, "algo": "permuted", "nnz": P},
+                   "rank": R, "algo": "permuted traversal over mode-sorted record copies",
+                   "nnz": P},
         "pct_of_hbm_peak": round(100.0 * main_res["gbs"] / HBM_PEAK_GBS, 1),
         "gflops": round(P * d * (d + 1) * R / (main_res["ms_per_step"] * 1e-3) / 1e9, 1),
+        "permuted_gather": {"gbs": round(gather_res["gbs"], 1),
+                            "ms_per_step": round(gather_res["ms_per_step"], 4),
+                            "note": "same traversal gathering each record through the permutation"},
         "atomic": {"gbs": round(atomic_res["gbs"], 1), "ms_per_step": round(atomic_res["ms_per_step"], 4),
-                   "permuted_speedup": round(atomic_res["ms_per_step"] / main_res["ms_per_step"], 3)},
+                   "permuted_speedup": round(atomic_res["ms_per_step"] / main_res["ms_per_step"], 3),
+                   "permuted_gather_speedup": round(atomic_res["ms_per_step"] / gather_res["ms_per_step"], 3)},
         "per_mode_ms": [round(x, 4) for x in main_res["per_mode_ms"]],
         "per_rank": per_rank,
         "extras": extras,

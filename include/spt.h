@@ -53,7 +53,11 @@ typedef enum spt_dtype { SPT_F64 = 0, SPT_F32 = 1, SPT_BF16 = 2 } spt_dtype;
 typedef enum spt_algo {
     SPT_ALGO_AUTO = 0,     /* library choice (tuned table, else the default heuristic) */
     SPT_ALGO_ATOMIC = 1,   /* storage-order traversal, LDS-combined partial rows + atomics */
-    SPT_ALGO_PERMUTED = 2  /* mode-sorted traversal, wave segmented reduction */
+    SPT_ALGO_PERMUTED = 2, /* mode-sorted traversal through the permutation (records gathered),
+                              wave segmented reduction */
+    SPT_ALGO_PERMUTED_COPY = 3 /* the same traversal reading a mode-sorted copy of the records
+                                  (spt_tensor_sort_copy): records stream instead of being
+                                  gathered; results identical to SPT_ALGO_PERMUTED */
 } spt_algo;
 
 /* Launch parameters of one MTTKRP.  Zero fields take the default.  A lane group of
@@ -113,6 +117,17 @@ int spt_tensor_permute(spt_tensor *X, int mode, void *stream);
 /* Device pointers of the mode's permutation and sorted keys (valid after spt_tensor_permute's
  * work completes, until the handle is destroyed); SPT_ESTATE if the mode is not permuted. */
 int spt_tensor_perm(const spt_tensor *X, int mode, const int32_t **perm, const int32_t **skey);
+
+/* Mode-sorted copies of the packed records (a memory-for-bandwidth trade the paper avoided for
+ * 12-16 GB GPUs, Sec. 5): the copy of mode n holds record perm_n[q] at position q, so the
+ * permuted MTTKRP streams records instead of gathering them.  Needs spt_tensor_permute(mode)
+ * first (SPT_ESTATE otherwise); mode = -1 copies every mode back to back.  ws: device buffer of
+ * at least spt_tensor_sorted_copy_bytes(X, mode) bytes, 256-byte aligned, caller-owned, kept
+ * alive until the copy is dropped or the handle destroyed.  A later spt_tensor_permute of a mode
+ * drops its copy.  With a copy present, SPT_ALGO_AUTO selects SPT_ALGO_PERMUTED_COPY. */
+size_t spt_tensor_sorted_copy_bytes(const spt_tensor *X, int mode);
+int spt_tensor_sort_copy(spt_tensor *X, int mode, void *ws, size_t ws_bytes, void *stream);
+int spt_tensor_drop_sorted_copy(spt_tensor *X, int mode);
 
 int spt_tensor_info(const spt_tensor *X, int *d, int64_t *dims, int64_t *nnz, int *vals_dtype);
 int spt_tensor_destroy(spt_tensor *X);

@@ -10,8 +10,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (ALGO_ATOMIC, ALGO_AUTO, ALGO_PERMUTED, SPT_BF16, SPT_F32, SPT_F64, SptError,
-                   SptTune, SptUnavailable)
+from ._lib import (ALGO_ATOMIC, ALGO_AUTO, ALGO_PERMUTED, ALGO_PERMUTED_COPY, SPT_BF16, SPT_F32,
+                   SPT_F64, SptError, SptTune, SptUnavailable)
 
 __all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPPoissonLoss",
            "default_tune", "autotune", "Batch", "to_bf16", "stream_triad", "SptError",
@@ -19,7 +19,10 @@ __all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPPo
            "ALGO_AUTO", "ALGO_ATOMIC", "ALGO_PERMUTED", "dtype_code"]
 
 _ALGOS = {"auto": ALGO_AUTO, "atomic": ALGO_ATOMIC, "permuted": ALGO_PERMUTED,
-          ALGO_AUTO: ALGO_AUTO, ALGO_ATOMIC: ALGO_ATOMIC, ALGO_PERMUTED: ALGO_PERMUTED}
+          "permuted_copy": ALGO_PERMUTED_COPY, ALGO_AUTO: ALGO_AUTO, ALGO_ATOMIC: ALGO_ATOMIC,
+          ALGO_PERMUTED: ALGO_PERMUTED, ALGO_PERMUTED_COPY: ALGO_PERMUTED_COPY}
+_ALGO_NAMES = {ALGO_AUTO: "auto", ALGO_ATOMIC: "atomic", ALGO_PERMUTED: "permuted",
+               ALGO_PERMUTED_COPY: "permuted_copy"}
 
 
 def _stream(stream=None):
@@ -94,6 +97,20 @@ class SparseTensor:
                    "spt_tensor_permute")
         return self
 
+    def sort_copy(self, mode: int = -1, stream=None):
+        """Build mode-sorted copies of the records (needs permute(mode) first); the permuted
+        MTTKRP then streams records instead of gathering them.  Costs one record array
+        (16 or 32 bytes per entry) per mode."""
+        lib = _lib.load()
+        nbytes = lib.spt_tensor_sorted_copy_bytes(self._h, int(mode))
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _lib.check(lib.spt_tensor_sort_copy(self._h, int(mode), ctypes.c_void_p(buf.data_ptr()),
+                                            nbytes, _stream(stream)), "spt_tensor_sort_copy")
+        if not hasattr(self, "_copies"):
+            self._copies = {}
+        self._copies[int(mode)] = buf
+        return self
+
     def validate(self, stream=None):
         bad = ctypes.c_int64(-1)
         rc = _lib.load().spt_tensor_validate(self._h, ctypes.byref(bad), _stream(stream))
@@ -136,7 +153,7 @@ def default_tune(X: SparseTensor, mode: int, R: int, fdtype, algo="auto") -> dic
     _lib.check(_lib.load().spt_mttkrp_default_tune(X.handle, int(mode), int(R),
                                                    dtype_code(fdtype), _ALGOS[algo],
                                                    ctypes.byref(t)), "default_tune")
-    return {"algo": t.algo, "lanes": t.lanes_per_nnz, "cols": t.cols_per_lane,
+    return {"algo": _ALGO_NAMES[t.algo], "lanes": t.lanes_per_nnz, "cols": t.cols_per_lane,
             "chunk": t.nnz_per_wave}
 
 
@@ -354,7 +371,7 @@ def autotune(X: SparseTensor, factors, mode: int, batch=False, algos=("atomic", 
                                        ctypes.c_void_p(out.data_ptr()), flags, int(reps),
                                        ctypes.byref(best), ctypes.byref(ms), _stream(stream)),
                "spt_mttkrp_autotune")
-    return {"algo": ["auto", "atomic", "permuted"][best.algo], "lanes": best.lanes_per_nnz,
+    return {"algo": _ALGO_NAMES[best.algo], "lanes": best.lanes_per_nnz,
             "cols": best.cols_per_lane, "chunk": best.nnz_per_wave, "ms": ms.value}
 
 

@@ -15,7 +15,7 @@ SPT_OK, SPT_EINVAL, SPT_ERANGE, SPT_EHIP, SPT_ESINGULAR = 0, -1, -2, -3, -4
 SPT_EWORKSPACE, SPT_EUNSUPPORTED, SPT_ESTATE = -5, -6, -7
 SPT_F64, SPT_F32, SPT_BF16 = 0, 1, 2
 TUNE_BATCH_CONFIGS, TUNE_NO_ATOMIC, TUNE_NO_PERMUTED = 1, 2, 4
-ALGO_AUTO, ALGO_ATOMIC, ALGO_PERMUTED = 0, 1, 2
+ALGO_AUTO, ALGO_ATOMIC, ALGO_PERMUTED, ALGO_PERMUTED_COPY = 0, 1, 2, 3
 
 _c_p = ctypes.c_void_p
 _c_i = ctypes.c_int
@@ -39,6 +39,9 @@ SIGNATURES = {
     "spt_tensor_status": (_c_i, [_c_p, _c_p]),
     "spt_tensor_permute": (_c_i, [_c_p, _c_i, _c_p]),
     "spt_tensor_perm": (_c_i, [_c_p, _c_i, _c_p, _c_p]),
+    "spt_tensor_sorted_copy_bytes": (_c_sz, [_c_p, _c_i]),
+    "spt_tensor_sort_copy": (_c_i, [_c_p, _c_i, _c_p, _c_sz, _c_p]),
+    "spt_tensor_drop_sorted_copy": (_c_i, [_c_p, _c_i]),
     "spt_tensor_info": (_c_i, [_c_p, _c_p, _c_p, _c_p, _c_p]),
     "spt_tensor_destroy": (_c_i, [_c_p]),
     "spt_mttkrp": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),

@@ -14,6 +14,7 @@ namespace spt {
 struct BatchItem {
     const int4 *rec;
     const int32_t *perm;
+    const int4 *srec;   // mode-sorted record copy or null
     const void *A[SPT_MAX_ORDER];
     void *V;
     int64_t P;
@@ -58,7 +59,7 @@ __device__ __forceinline__ void batch_unit(int4 *smem4, const BatchItem &it, int
         const int wave = threadIdx.x >> 6;
         const int64_t c0 = bc0 + (int64_t)wave * it.chunk;
         if (c0 < it.P)
-            perm_wave_chunk<D, G, CPL, FT, float, float>(sm[wave], it.rec, it.perm, it.P, it.n,
+            perm_wave_chunk<D, G, CPL, FT, float, float>(sm[wave], it.rec, it.perm, it.srec, it.P, it.n,
                                                          it.R, A, nullptr, nullptr, V, it.chunk, c0);
     } else {
         atomic_block_unit<D, G, CPL, FT, float, float>(smem4, it.rec, it.P, it.n, it.R, A, nullptr,
@@ -157,6 +158,7 @@ extern "C" {
 
 int spt_batch_supported_tune(int d, int fdtype, int algo, int lanes_per_nnz, int cols_per_lane) {
     if (fdtype != SPT_F32 && fdtype != SPT_BF16) return 0;
+    if (algo == SPT_ALGO_PERMUTED_COPY) algo = SPT_ALGO_PERMUTED;
     return batch_cfg_index(algo, d, lanes_per_nnz, cols_per_lane) >= 0;
 }
 
@@ -189,12 +191,15 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         rc = resolve_tune(X, n, R, fdtype, &tunes[i], &t);
         if (rc) return rc;
         if (t.algo == SPT_ALGO_PERMUTED && !X->permuted[n]) return SPT_ESTATE;
-        const int cfg = batch_cfg_index(t.algo, X->d, t.lanes_per_nnz, t.cols_per_lane);
+        if (t.algo == SPT_ALGO_PERMUTED_COPY && X->srec[n] == nullptr) return SPT_ESTATE;
+        const int kalgo = (t.algo == SPT_ALGO_PERMUTED_COPY) ? SPT_ALGO_PERMUTED : t.algo;
+        const int cfg = batch_cfg_index(kalgo, X->d, t.lanes_per_nnz, t.cols_per_lane);
         if (cfg < 0) return SPT_EUNSUPPORTED;
         BatchItem &b = h[i];
         memset(&b, 0, sizeof b);
         b.rec = X->rec;
         b.perm = X->perm[n];
+        b.srec = (t.algo == SPT_ALGO_PERMUTED_COPY) ? X->srec[n] : nullptr;
         for (int m = 0; m < X->d; ++m) b.A[m] = factors[i][m];
         b.V = outputs[i];
         b.P = X->P;

@@ -512,6 +512,7 @@ int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fd
     rc = resolve_tune(X, mode, R, fdtype, tune, &t);
     if (rc) return rc;
     if (t.algo == SPT_ALGO_PERMUTED && !X->permuted[mode]) return SPT_ESTATE;
+    if (t.algo == SPT_ALGO_PERMUTED_COPY && X->srec[mode] == nullptr) return SPT_ESTATE;
     // V = MTTKRP with the other (normalised) factors and unit weights
     rc = launch_mttkrp(X, mode, R, (const void *const *)factors, fdtype, nullptr, nullptr, V, t, s);
     if (rc) return rc;

@@ -91,6 +91,8 @@ int spt_gcp_poisson_backward(const spt_tensor *X, int R, const void *const *fact
         rc = resolve_tune(X, n, R, fdtype, tune, &t);
         if (rc) return rc;
         if (t.algo == SPT_ALGO_PERMUTED && !X->permuted[n]) t.algo = SPT_ALGO_ATOMIC;
+        if (t.algo == SPT_ALGO_PERMUTED_COPY && X->srec[n] == nullptr)
+            t.algo = X->permuted[n] ? SPT_ALGO_PERMUTED : SPT_ALGO_ATOMIC;
         rc = launch_mttkrp(X, n, R, factors, fdtype, nullptr, y, grads[n], t, s);
         if (rc) return rc;
     }

@@ -103,11 +103,16 @@ static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out
 int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tune *in,
                  spt_tune *out) {
     spt_tune t = in ? *in : spt_tune{0, 0, 0, 0};
-    if (t.algo == SPT_ALGO_AUTO) t.algo = X->permuted[mode] ? SPT_ALGO_PERMUTED : SPT_ALGO_ATOMIC;
-    if (t.algo != SPT_ALGO_ATOMIC && t.algo != SPT_ALGO_PERMUTED) return SPT_EINVAL;
+    if (t.algo == SPT_ALGO_AUTO)
+        t.algo = X->srec[mode] != nullptr ? SPT_ALGO_PERMUTED_COPY
+                                          : (X->permuted[mode] ? SPT_ALGO_PERMUTED : SPT_ALGO_ATOMIC);
+    if (t.algo != SPT_ALGO_ATOMIC && t.algo != SPT_ALGO_PERMUTED &&
+        t.algo != SPT_ALGO_PERMUTED_COPY)
+        return SPT_EINVAL;
+    const int lalgo = (t.algo == SPT_ALGO_ATOMIC) ? SPT_ALGO_ATOMIC : SPT_ALGO_PERMUTED;
     int G = t.lanes_per_nnz, cpl = t.cols_per_lane;
     if (G == 0 && cpl == 0) {
-        default_layout(R, fdtype, t.algo, &G, &cpl);
+        default_layout(R, fdtype, lalgo, &G, &cpl);
     } else if (cpl == 0) {
         cpl = (R + G - 1) / G;
         while (cpl & (cpl - 1)) ++cpl;
@@ -121,7 +126,7 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
     if (t.nnz_per_wave == 0) {
         // long chunks amortise the chunk-boundary work, but a small tensor needs enough
         // wavefronts to occupy the GPU: aim for at least ~2048 wave chunks
-        const int64_t cap = (t.algo == SPT_ALGO_PERMUTED) ? 4096 : 2048;
+        const int64_t cap = (lalgo == SPT_ALGO_PERMUTED) ? 4096 : 2048;
         int64_t c = (X->P / 2048) & ~int64_t(63);
         t.nnz_per_wave = (int)(c < 256 ? 256 : (c > cap ? cap : c));
     }
@@ -143,6 +148,7 @@ int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *facto
     MttkrpArgs a;
     a.rec = X->rec;
     a.perm = X->perm[mode];
+    a.srec = (t.algo == SPT_ALGO_PERMUTED_COPY) ? X->srec[mode] : nullptr;
     a.P = X->P;
     a.n = mode;
     a.R = R;
@@ -205,6 +211,7 @@ extern "C" int spt_mttkrp(const spt_tensor *X, int mode, int R, const void *cons
     rc = resolve_tune(X, mode, R, fdtype, tune, &t);
     if (rc) return rc;
     if (t.algo == SPT_ALGO_PERMUTED && !X->permuted[mode]) return SPT_ESTATE;
+    if (t.algo == SPT_ALGO_PERMUTED_COPY && X->srec[mode] == nullptr) return SPT_ESTATE;
     return launch_mttkrp(X, mode, R, factors, fdtype, lambda, vals, V, t,
                          static_cast<hipStream_t>(stream));
 }
@@ -261,8 +268,11 @@ extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
     spt_tune bt{0, 0, 0, 0};
     int tried = 0;
     rc = SPT_OK;
-    for (int algo = SPT_ALGO_ATOMIC; algo <= SPT_ALGO_PERMUTED && rc == SPT_OK; ++algo) {
+    for (int algo = SPT_ALGO_ATOMIC; algo <= SPT_ALGO_PERMUTED_COPY && rc == SPT_OK; ++algo) {
         if (algo == SPT_ALGO_PERMUTED && (!X->permuted[mode] || (flags & SPT_TUNE_NO_PERMUTED)))
+            continue;
+        if (algo == SPT_ALGO_PERMUTED_COPY &&
+            (X->srec[mode] == nullptr || (flags & SPT_TUNE_NO_PERMUTED)))
             continue;
         if (algo == SPT_ALGO_ATOMIC && (flags & SPT_TUNE_NO_ATOMIC)) continue;
         for (const auto &c : cfgs) {
@@ -271,6 +281,8 @@ extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
             if (G * CPL < R || R % CPL != 0) continue;
             if (G * CPL >= 2 * R && G * CPL > 16) continue;
             if (batch_only && !spt_batch_supported_tune(X->d, fdtype, algo, G, CPL)) continue;
+            const int lalgo = (algo == SPT_ALGO_ATOMIC) ? SPT_ALGO_ATOMIC : SPT_ALGO_PERMUTED;
+            (void)lalgo;
             for (int chunk : chunks) {
                 spt_tune t{algo, G, CPL, chunk}, r;
                 if (resolve_tune(X, mode, R, fdtype, &t, &r) != SPT_OK) continue;

@@ -196,7 +196,8 @@ struct PermShared {
 template <int D, int G, int CPL, class FT, class VT, class AT>
 __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &sm,
                                                 const int4 *__restrict__ rec,
-                                                const int32_t *__restrict__ perm, int64_t P,
+                                                const int32_t *__restrict__ perm,
+                                                const int4 *__restrict__ srec, int64_t P,
                                                 int n, int R, const FactorSet<FT> &A,
                                                 const double *__restrict__ lambda,
                                                 const VT *__restrict__ vovr, AT *__restrict__ V,
@@ -227,18 +228,26 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
         sm.pkey[2 * g + 1] = -1;
     }
 
-    // software pipeline: the records of batch b+1 and the permutation entries of batch b+2
-    // are in flight while batch b is processed
+    // software pipeline: the records of batch b+1 (and, when they are gathered through the
+    // permutation, the permutation entries of batch b+2) are in flight while batch b is
+    // processed.  With a mode-sorted copy of the records (srec) the records stream in order.
+    const int4 *gsrec = (srec != nullptr) ? srec + gb * RQ : nullptr;
     int4 rc0 = make_int4(0, 0, 0, 0), rc1 = rc0;
     VT vo = 0;
     int pn = -1;
     if (gl < glen) {
-        const int p = gperm[gl];
-        rc0 = rec[(int64_t)p * RQ];
-        if constexpr (RQ == 2) rc1 = rec[(int64_t)p * RQ + 1];
-        if (vovr != nullptr) vo = vovr[p];
+        if (gsrec != nullptr) {
+            rc0 = gsrec[gl * RQ];
+            if constexpr (RQ == 2) rc1 = gsrec[gl * RQ + 1];
+            if (vovr != nullptr) vo = vovr[gperm[gl]];
+        } else {
+            const int p = gperm[gl];
+            rc0 = rec[(int64_t)p * RQ];
+            if constexpr (RQ == 2) rc1 = rec[(int64_t)p * RQ + 1];
+            if (vovr != nullptr) vo = vovr[p];
+        }
     }
-    if (G + gl < glen) pn = gperm[G + gl];
+    if (gsrec == nullptr && G + gl < glen) pn = gperm[G + gl];
 
     int key = -1, first_key = -1;
     AT acc[CPL];
@@ -253,12 +262,21 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                 rec_set_value<VT, RW>(reinterpret_cast<int *>(&sm.rec[lane * RQ]), vo);
         }
         wave_sync();
-        if (pn >= 0) {
-            rc0 = rec[(int64_t)pn * RQ];
-            if constexpr (RQ == 2) rc1 = rec[(int64_t)pn * RQ + 1];
-            if (vovr != nullptr) vo = vovr[pn];
+        if (gsrec != nullptr) {
+            const int nx = (b + 1) * G + gl;
+            if (nx < glen) {
+                rc0 = gsrec[nx * RQ];
+                if constexpr (RQ == 2) rc1 = gsrec[nx * RQ + 1];
+                if (vovr != nullptr) vo = vovr[gperm[nx]];
+            }
+        } else {
+            if (pn >= 0) {
+                rc0 = rec[(int64_t)pn * RQ];
+                if constexpr (RQ == 2) rc1 = rec[(int64_t)pn * RQ + 1];
+                if (vovr != nullptr) vo = vovr[pn];
+            }
+            pn = ((b + 2) * G + gl < glen) ? gperm[(b + 2) * G + gl] : -1;
         }
-        pn = ((b + 2) * G + gl < glen) ? gperm[(b + 2) * G + gl] : -1;
 
         const int cnt = glen - b * G < G ? glen - b * G : G;
         const int4 *sr = &sm.rec[g * G * RQ];
@@ -345,14 +363,16 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
 
 template <int D, int G, int CPL, class FT, class VT, class AT>
 __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
-    const int4 *__restrict__ rec, const int32_t *__restrict__ perm, int64_t P, int n, int R,
+    const int4 *__restrict__ rec, const int32_t *__restrict__ perm,
+    const int4 *__restrict__ srec, int64_t P, int n, int R,
     FactorSet<FT> A, const double *__restrict__ lambda, const VT *__restrict__ vovr,
     AT *__restrict__ V, int chunk) {
     __shared__ PermShared<D, G, CPL, VT, AT> sm[kBlock / kWave];
     const int wave = threadIdx.x >> 6;
     const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
     if (c0 >= P) return;  // whole wavefront leaves together
-    perm_wave_chunk<D, G, CPL, FT, VT, AT>(sm[wave], rec, perm, P, n, R, A, lambda, vovr, V, chunk, c0);
+    perm_wave_chunk<D, G, CPL, FT, VT, AT>(sm[wave], rec, perm, srec, P, n, R, A, lambda, vovr, V,
+                                           chunk, c0);
 }
 
 // One workgroup processes storage positions [bc0, bc0 + 4 chunk) (one chunk per wavefront)
@@ -477,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
 struct MttkrpArgs {
     const int4 *rec;
     const int32_t *perm;
+    const int4 *srec;
     int64_t P;
     int n, R;
     const double *lambda;
@@ -501,9 +522,10 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
     const int64_t per_block = (int64_t)a.chunk * (kBlock / kWave);
     const unsigned grid = (unsigned)ceil_div(a.P, per_block);
     if (grid == 0) return SPT_OK;
-    if (a.algo == SPT_ALGO_PERMUTED) {
+    if (a.algo == SPT_ALGO_PERMUTED || a.algo == SPT_ALGO_PERMUTED_COPY) {
         hipLaunchKernelGGL((k_mttkrp_perm<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock), 0,
-                           a.stream, a.rec, a.perm, a.P, a.n, a.R, A, a.lambda, vovr, V, a.chunk);
+                           a.stream, a.rec, a.perm, a.srec, a.P, a.n, a.R, A, a.lambda, vovr, V,
+                           a.chunk);
     } else {
         const int H = a.hbits > 0 ? (1 << a.hbits) : 0;
         const size_t smem = atomic_smem_bytes<AT>(RecShape<D, VT>::RQ, H, G * CPL);

@@ -27,6 +27,7 @@ struct spt_tensor {
     int4 *rec;           // P packed records: subscripts in words 0..d-1, value in the last word(s)
     int32_t *perm[SPT_MAX_ORDER];
     int32_t *skey[SPT_MAX_ORDER];
+    int4 *srec[SPT_MAX_ORDER];  // optional mode-sorted record copies (caller workspace)
     int32_t *tmp_keys;   // radix-sort ping-pong buffers
     int32_t *tmp_vals;
     uint32_t *hist;      // 256 x ntiles digit counts, scanned in place

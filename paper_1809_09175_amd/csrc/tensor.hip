@@ -225,6 +225,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     }
 }
 
+// Mode-sorted copy of the records: out[q] = rec[perm[q]] (coalesced writes, gathered reads).
+template <int RQ>
+__global__ __launch_bounds__(kBlock) void k_gather_records(const int4 *__restrict__ rec,
+                                                           const int32_t *__restrict__ perm,
+                                                           int64_t P, int4 *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P; q += stride) {
+        const int64_t p = perm[q];
+        out[q * RQ] = rec[p * RQ];
+        if constexpr (RQ == 2) out[q * RQ + 1] = rec[p * RQ + 1];
+    }
+}
+
 __global__ void k_iota_perm(int32_t *perm, int32_t *skey, int64_t P) {
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < P) {
@@ -244,6 +257,7 @@ static int bit_width(int64_t x) {  // bits needed for values 0..x
 
 static int permute_mode(spt_tensor *X, int n, hipStream_t s) {
     const int64_t P = X->P;
+    X->srec[n] = nullptr;
     if (P == 0) {
         X->permuted[n] = 1;
         return SPT_OK;
@@ -467,6 +481,48 @@ int spt_tensor_permute(spt_tensor *X, int mode, void *stream) {
         int rc = permute_mode(X, n, s);
         if (rc) return rc;
     }
+    return SPT_OK;
+}
+
+size_t spt_tensor_sorted_copy_bytes(const spt_tensor *X, int mode) {
+    if (X == nullptr || mode < -1 || mode >= X->d) return 0;
+    const size_t one = align256((size_t)X->P * X->rec_words * 4);
+    return mode == -1 ? one * X->d : one;
+}
+
+int spt_tensor_sort_copy(spt_tensor *X, int mode, void *ws, size_t ws_bytes, void *stream) {
+    if (X == nullptr || mode < -1 || mode >= X->d) return SPT_EINVAL;
+    const size_t need = spt_tensor_sorted_copy_bytes(X, mode);
+    if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < need) return SPT_EWORKSPACE;
+    for (int n = 0; n < X->d; ++n)
+        if ((mode == -1 || n == mode) && !X->permuted[n]) return SPT_ESTATE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    const size_t one = align256((size_t)X->P * X->rec_words * 4);
+    for (int n = 0; n < X->d; ++n) {
+        if (mode != -1 && n != mode) continue;
+        int4 *dst = reinterpret_cast<int4 *>(w);
+        w += one;
+        if (X->P > 0) {
+            int64_t blocks = ceil_div(X->P, kBlock);
+            if (blocks > 65536) blocks = 65536;
+            if (X->rec_words == 4)
+                hipLaunchKernelGGL(k_gather_records<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                                   X->rec, X->perm[n], X->P, dst);
+            else
+                hipLaunchKernelGGL(k_gather_records<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                                   X->rec, X->perm[n], X->P, dst);
+            SPT_LAUNCH_CHECK();
+        }
+        X->srec[n] = dst;
+    }
+    return SPT_OK;
+}
+
+int spt_tensor_drop_sorted_copy(spt_tensor *X, int mode) {
+    if (X == nullptr || mode < -1 || mode >= X->d) return SPT_EINVAL;
+    for (int n = 0; n < X->d; ++n)
+        if (mode == -1 || n == mode) X->srec[n] = nullptr;
     return SPT_OK;
 }
 

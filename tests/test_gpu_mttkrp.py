@@ -264,3 +264,36 @@ def test_powerlaw3_full_size_sampled(gpu):
             assert _relerr(got, V_ref) < TOL["f32"], (n, algo)
             # the hot row alone (the FP32 accuracy risk: 12.7% of all entries)
             assert _relerr(got[rows == hot], V_ref[rows == hot]) < TOL["f32"]
+
+
+@pytest.mark.parametrize("kind,R,d", [("f32", 32, 3), ("f32", 16, 4), ("bf16", 32, 3), ("f64", 16, 3)])
+def test_sorted_copy_matches_gathered(gpu, kind, R, d):
+    """The mode-sorted record copy changes where records are read from, not the traversal: both
+    kernels sum every row in the same order, so they agree to the rounding of the (at most two
+    per wave chunk) boundary atomics, whose order is not fixed; with and without replacement
+    values, and both match the oracle."""
+    import paper_1809_09175_amd as spt
+    dims = (900, 700, 60, 30)[:d]
+    X = _small(kind, dims, 70_001, (1.1,) * d, seed=77)
+    T = _dev_tensor(X, np.float64 if kind == "f64" else np.float32)
+    T.permute()
+    T.sort_copy()
+    dev, ref = _factors(dims, R, seed=5, kind=kind)
+    y = torch.from_numpy(np.random.default_rng(1).standard_normal(X.nnz).astype(
+        np.float64 if kind == "f64" else np.float32)).cuda()
+    for n in range(d):
+        assert spt.default_tune(T, n, R, dev[0].dtype)["algo"] == "permuted_copy"
+        for vals in (None, y):
+            a = spt.mttkrp(T, dev, n, algo="permuted", vals=vals)
+            b = spt.mttkrp(T, dev, n, algo="permuted_copy", vals=vals)
+            torch.cuda.synchronize()
+            tight = 1e-14 if kind == "f64" else 1e-6
+            assert _relerr(a.cpu().numpy(), b.cpu().numpy().astype(np.float64)) < tight, n
+        V_ref = oracle.mttkrp(X.subs, X.vals, dims, ref, n)
+        assert _relerr(spt.mttkrp(T, dev, n).cpu().numpy(), V_ref) < TOL[kind]
+    # re-permuting a mode drops its copy; the permuted-copy kernel then reports the state error
+    from paper_1809_09175_amd import SptError
+    T.permute(0)
+    with pytest.raises(SptError) as e:
+        spt.mttkrp(T, dev, 0, algo="permuted_copy")
+    assert e.value.code == -7
