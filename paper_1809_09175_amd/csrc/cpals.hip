@@ -118,13 +118,23 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const FT *__restrict__ 
     }
 }
 
+// out[i] = sum over the partials b = 0..nblk-1 in order (deterministic); one thread per entry,
+// the loads of consecutive partials issued ahead of the additions
 __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__ part, int nblk,
                                                       int len, double *__restrict__ out) {
-    for (int i = threadIdx.x; i < len; i += kBlock) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * len + i];
-        out[i] = s;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = part[(int64_t)(b + k) * len + i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
     }
+    for (; b < nblk; ++b) s += part[(int64_t)b * len + i];
+    out[i] = s;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -232,18 +242,23 @@ __global__ void k_norms_from_gram(const double *__restrict__ GY, int R, double *
 // ------------------------------------------------------------------------------------------
 enum { KIND_FIT = 0, KIND_VALUES = 1, KIND_GCP = 2 };
 
-template <int D, int G, class FT, class VT, class CT, int KIND>
+template <int D, int G, int CPL, class FT, class VT, class CT, int KIND>
 __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, int64_t P, int R,
                                                   FactorSet<FT> A, const double *__restrict__ lambda,
                                                   const CT *__restrict__ w, void *__restrict__ mout,
                                                   double *__restrict__ part, int chunk) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
-    constexpr int U = 4;
+    constexpr int U = UnrollFor<CPL, G>::value;
     __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane / G, gl = lane % G;
-    const bool colok = gl < R;
-    const CT lam = (lambda != nullptr && colok) ? (CT)lambda[gl] : (CT)1;
+    const int col0 = gl * CPL;
+    const bool colok = col0 < R;
+    const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
+    CT lam[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+        lam[c] = (lambda != nullptr && colok) ? (CT)lambda[col0 + c] : (CT)1;
     double s0acc = 0.0, s1acc = 0.0;
     const int64_t nchunks = ceil_div(P, chunk);
     for (int64_t ch = (int64_t)blockIdx.x * (kBlock / kWave) + wave; ch < nchunks;
@@ -268,23 +283,26 @@ __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, 
                     x[u] = 0;
                     if (u0 + u < cnt) {
                         int wv[RW];
-                        const int4 *q = &s_rec[wave][(g * G + u0 + u) * RQ];
-                        int4 a = q[0];
-                        wv[0] = a.x; wv[1] = a.y; wv[2] = a.z; wv[3] = a.w;
-                        if constexpr (RQ == 2) {
-                            int4 bq = q[1];
-                            wv[4] = bq.x; wv[5] = bq.y; wv[6] = bq.z; wv[7] = bq.w;
-                        }
+                        lds_record<RQ>(&s_rec[wave][(g * G + u0 + u) * RQ], wv);
                         x[u] = rec_value<VT, RW>(wv);
                         if (colok) {
-                            CT p = lam;
+                            // lambda_j prod_m A^(m)(l_m, j) for this lane's columns, then their sum
+                            CT p[CPL];
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c) p[c] = lam[c];
 #pragma unroll
                             for (int m = 0; m < D; ++m) {
-                                CT f[1];
-                                load_cols<FT, 1, CT>(A.p[m] + (int64_t)wv[m] * R + gl, f);
-                                p *= f[0];
+                                CT f[CPL];
+                                const uint32_t off = (uint32_t)wv[m] * rowbytes + colbytes;
+                                load_cols<FT, CPL, CT>(reinterpret_cast<const FT *>(
+                                                           reinterpret_cast<const char *>(A.p[m]) + off), f);
+#pragma unroll
+                                for (int c = 0; c < CPL; ++c) p[c] *= f[c];
                             }
-                            t[u] = p;
+                            CT q = p[0];
+#pragma unroll
+                            for (int c = 1; c < CPL; ++c) q += p[c];
+                            t[u] = q;
                         }
                     }
                 }
@@ -365,10 +383,20 @@ __global__ __launch_bounds__(kBlock) void k_loss_final(const double *__restrict_
 // host side
 // ------------------------------------------------------------------------------------------
 
-static int group_for(int R) {
-    int G = 8;
-    while (G < R) G <<= 1;
-    return G;
+// lane layout of the model-value pass: 8 lanes per entry with up to 8 columns each (wide
+// loads, a 3-step group reduction), else one column per lane
+static void model_layout(int R, int *G, int *CPL) {
+    const int opts[] = {8, 4, 2, 1};
+    for (int c : opts)
+        if (R % c == 0 && R / c <= 8) {
+            *G = 8;
+            *CPL = c;
+            return;
+        }
+    int g = 16;
+    while (g < R) g <<= 1;
+    *G = g;
+    *CPL = 1;
 }
 
 template <int D, class FT, class VT, class CT, int KIND>
@@ -381,20 +409,24 @@ static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
     if (nblk > 2048) nblk = 2048;
     if (nblk < 1) nblk = 1;
     *nblk_out = (int)nblk;
-    const int G = group_for(R);
-#define SPT_MODEL_G(GG)                                                                       \
-    case GG:                                                                                  \
-        hipLaunchKernelGGL((k_model<D, GG, FT, VT, CT, KIND>), dim3((unsigned)nblk), dim3(kBlock), \
-                           0, s, X->rec, X->P, R, A, lambda, w, mout, part, chunk);          \
+    int G = 8, CPL = 1;
+    model_layout(R, &G, &CPL);
+#define SPT_MODEL_CFG(GG, CC)                                                                  \
+    case GG * 16 + CC:                                                                         \
+        hipLaunchKernelGGL((k_model<D, GG, CC, FT, VT, CT, KIND>), dim3((unsigned)nblk),        \
+                           dim3(kBlock), 0, s, X->rec, X->P, R, A, lambda, w, mout, part, chunk); \
         break;
-    switch (G) {
-        SPT_MODEL_G(8)
-        SPT_MODEL_G(16)
-        SPT_MODEL_G(32)
-        SPT_MODEL_G(64)
+    switch (G * 16 + CPL) {
+        SPT_MODEL_CFG(8, 1)
+        SPT_MODEL_CFG(8, 2)
+        SPT_MODEL_CFG(8, 4)
+        SPT_MODEL_CFG(8, 8)
+        SPT_MODEL_CFG(16, 1)
+        SPT_MODEL_CFG(32, 1)
+        SPT_MODEL_CFG(64, 1)
         default: return SPT_EUNSUPPORTED;
     }
-#undef SPT_MODEL_G
+#undef SPT_MODEL_CFG
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }
 
@@ -418,9 +450,12 @@ static int64_t max_dim(const spt_tensor *X) {
     return m;
 }
 
+// partial Grams per call: one per CU-ish, each workgroup covering many 64-row tiles, so the
+// final (sequential, deterministic) sum over partials stays short
+constexpr int kGramBlocks = 256;
 static int gram_blocks(int64_t I) {
     int64_t b = ceil_div(I, kGramRows);
-    if (b > kMaxPartBlocks) b = kMaxPartBlocks;
+    if (b > kGramBlocks) b = kGramBlocks;
     return (int)(b < 1 ? 1 : b);
 }
 
@@ -430,7 +465,8 @@ static int launch_gram(const FT *Ain, const double *Y, const double *lambda, FT 
     const int nb = gram_blocks(I);
     hipLaunchKernelGGL((k_gram_partial<FT, NORM>), dim3(nb), dim3(kBlock), 0, s, Ain, Y, lambda,
                        Aout, I, R, gpart);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(kBlock), 0, s, gpart, nb, R * R, G);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)ceil_div(R * R, kBlock)), dim3(kBlock), 0, s,
+                       gpart, nb, R * R, G);
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }
 
