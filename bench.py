@@ -36,16 +36,18 @@ def model_bytes(d, R, s_val=4, s_idx=4, s_f=4, s_out=4):
 
 
 def kernel_source_hash():
+    """Hash of the sources the MTTKRP kernels are compiled from (not the host launch code)."""
     h = hashlib.sha256()
-    for f in ("mttkrp_kernels.h", "mttkrp.hip", "mttkrp_f32.hip", "spt_internal.h"):
+    for f in ("mttkrp_kernels.h", "mttkrp_f32.hip", "spt_internal.h"):
         with open(os.path.join(ROOT, "paper_1809_09175_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_counters():
+def read_counters(kernel_name):
     """HBM traffic per dispatch of the dominant kernel, from the committed rocprofv3 counter
-    summary; None when absent or taken from a different kernel source."""
+    summary; None when absent, taken for another kernel instantiation, or taken from a
+    different kernel source."""
     path = os.path.join(ROOT, "profiles", "mttkrp_perm_powerlaw3_R32_counters.txt")
     if not os.path.exists(path):
         return None
@@ -54,7 +56,7 @@ def read_counters():
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash():
+    if kv.get("kernel_source_hash") != kernel_source_hash() or kv.get("kernel") != kernel_name:
         return None
     try:
         return float(kv["hbm_bytes_per_dispatch"])
@@ -183,6 +185,44 @@ def bench_batch64(spt, datagen, torch, dev, reps=10):
     return res
 
 
+def bench_gcp(spt, datagen, torch, dev, R=32, steps=3):
+    """Generalized CP (Poisson log link) forward + backward on the count tensor: 5e7 nonzeros
+    plus 5e7 sampled zeros; the backward is one MTTKRP per mode of the derivative tensor."""
+    t0 = time.time()
+    X, A = datagen.gcp_counts(R=R)
+    log(f"generated gcp_counts ({X.nnz} entries) in {time.time() - t0:.1f}s")
+    T = spt.SparseTensor(torch.from_numpy(X.subs).to(dev), torch.from_numpy(X.vals).to(dev), X.dims)
+    T.validate()
+    T.permute()
+    T.sort_copy()
+    facs = [torch.from_numpy(a).to(dev).requires_grad_(True) for a in A]
+
+    def step():
+        for f in facs:
+            f.grad = None
+        loss = spt.GCPPoissonLoss.apply(T, None, *facs)
+        loss.backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        loss = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    per_entry = (16 + X.d * R * 4 + 4) + X.d * model_bytes(X.d, R)
+    res = {"entries": X.nnz, "rank": R, "ms_fwd_bwd": round(ms, 3),
+           "model_gbs": round(X.nnz * per_entry / (ms * 1e-3) / 1e9, 1),
+           "loss": float(loss.item())}
+    log(f"gcp fwd+bwd {ms:.3f} ms")
+    del T, facs
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,8 +232,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="skip the extra workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: R=32 permuted and atomic, 2 steps each, plus "
-                         "one triad over 3 x 1 GiB (the counter calibration kernel)")
+                    help="short run for rocprofv3: R=32 permuted (sorted copies) and atomic, 2 "
+                         "steps each, plus one triad over 3 x 1 GiB (the counter calibration "
+                         "kernel)")
+    ap.add_argument("--profile-gather", action="store_true",
+                    help="as --profile, with the permuted kernel gathering records through the "
+                         "permutation instead of reading the sorted copies")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -278,6 +322,8 @@ def main():
                 "wall_s": wall}
 
     R = args.rank
+    if args.profile_gather:
+        args.profile = True
     # mode-sorted record copies: built once, like the permutations
     T.sort_copy()
     torch.cuda.synchronize()
@@ -292,9 +338,10 @@ def main():
         spt.stream_triad(a, b, c)
         torch.cuda.synchronize()
         del a, b, c
-    main_res = measure(R, "permuted_copy", args.steps, args.warmup)
+    main_res = measure(R, "permuted" if args.profile_gather else "permuted_copy", args.steps,
+                       args.warmup)
     log(f"R={R} permuted (sorted copies): {main_res['ms_per_step']:.3f} ms/step, {main_res['gbs']:.0f} GB/s")
-    gather_res = measure(R, "permuted", max(2, args.steps // 2), 1 if args.profile else 2)
+    gather_res = main_res if args.profile else measure(R, "permuted", max(2, args.steps // 2), 2)
     log(f"R={R} permuted (gather): {gather_res['ms_per_step']:.3f} ms/step, {gather_res['gbs']:.0f} GB/s")
     atomic_res = measure(R, "atomic", max(2, args.steps // 2), 1 if args.profile else 2)
     log(f"R={R} atomic:   {atomic_res['ms_per_step']:.3f} ms/step, {atomic_res['gbs']:.0f} GB/s")
@@ -358,17 +405,19 @@ def main():
         log(f"triad {triad_gbs:.0f} GB/s")
         extras["skewed4_bf16_vs_fp32"] = bench_skewed4_bf16(spt, datagen, torch, dev)
         extras["batch64"] = bench_batch64(spt, datagen, torch, dev)
+        extras["gcp_poisson"] = bench_gcp(spt, datagen, torch, dev)
 
     # roofline of the dominant kernel (the permuted MTTKRP); per launch = one mode
     dtune = spt.default_tune(T, 0, R, torch.float32, algo="permuted_copy")
     avg_launch_ms = float(np.mean(main_res["per_mode_ms"]))
     per_launch_bytes = P * model_bytes(d, R)
     achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
-    traffic = read_counters()
+    kname = f"spt::k_mttkrp_perm<3, {dtune['lanes']}, {dtune['cols']}, float, float, float>"
+    traffic = read_counters(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "k_mttkrp_perm<3," + str(dtune["lanes"]) + "," + str(dtune["cols"]) + ",float> (sorted record copies)",
+                "kernel": kname + " reading the sorted record copies",
                 "per_launch_model_bytes": per_launch_bytes,
                 "avg_launch_ms": round(avg_launch_ms, 4)}
 

@@ -232,29 +232,25 @@ def batch64(count=64, seed0=4000, nnz_range=(1e4, 2e6), dim_range=(1e3, 5e4)):
 
 
 def gcp_counts(scale=1.0, dims=(200_000, 100_000, 5_000), seed=5, R=32):
-    """Nonzeros (zero-truncated Poisson(2) counts) followed by sampled zeros, weights 1."""
+    """Nonzeros (zero-truncated Poisson(2) counts) followed by sampled zeros, weights 1.
+
+    2 * nz distinct cells are drawn uniformly (draw, dedupe, top up), put in random order, and
+    split: the first nz are the nonzeros, the rest the sampled zeros (so the two sets are
+    disjoint)."""
     rng = np.random.default_rng(seed)
     nz = max(1, int(round(5e7 * scale)))
     nzero = nz
     cells = 1
     for I in dims:
         cells *= int(I)
-    lin = np.empty(0, dtype=np.int64)
-    while lin.size < nz:
-        more = rng.integers(0, cells, size=int((nz - lin.size) * 1.01) + 16, dtype=np.int64)
-        cat = np.concatenate([lin, more])
-        _, first = np.unique(cat, return_index=True)
-        first.sort()
-        lin = cat[first[:nz]]
-    zeros = np.empty(0, dtype=np.int64)
-    nz_sorted = np.sort(lin)
-    while zeros.size < nzero:
-        more = rng.integers(0, cells, size=int((nzero - zeros.size) * 1.01) + 16, dtype=np.int64)
-        more = more[~np.isin(more, nz_sorted, assume_unique=False)]
-        cat = np.concatenate([zeros, more])
-        _, first = np.unique(cat, return_index=True)
-        first.sort()
-        zeros = cat[first[:nzero]]
+    if nz + nzero > cells:
+        raise ValueError("more entries than cells")
+    u = np.unique(rng.integers(0, cells, size=int((nz + nzero) * 1.001) + 16, dtype=np.int64))
+    while u.size < nz + nzero:
+        u = np.unique(np.concatenate([u, rng.integers(0, cells, size=nz + nzero - u.size + 16,
+                                                      dtype=np.int64)]))
+    u = u[rng.permutation(u.size)[:nz + nzero]]
+    lin, zeros = u[:nz], u[nz:]
     counts = rng.poisson(2.0, size=nz)
     while True:
         bad = np.flatnonzero(counts == 0)
