@@ -55,9 +55,14 @@ typedef enum spt_algo {
     SPT_ALGO_ATOMIC = 1,   /* storage-order traversal, LDS-combined partial rows + atomics */
     SPT_ALGO_PERMUTED = 2, /* mode-sorted traversal through the permutation (records gathered),
                               wave segmented reduction */
-    SPT_ALGO_PERMUTED_COPY = 3 /* the same traversal reading a mode-sorted copy of the records
-                                  (spt_tensor_sort_copy): records stream instead of being
-                                  gathered; results identical to SPT_ALGO_PERMUTED */
+    SPT_ALGO_PERMUTED_COPY = 3, /* the same traversal reading a mode-sorted copy of the records
+                                   (spt_tensor_sort_copy): records stream instead of being
+                                   gathered; results identical to SPT_ALGO_PERMUTED */
+    SPT_ALGO_PRIVATIZED = 4 /* storage-order traversal into a per-workgroup LDS copy of the whole
+                               output, flushed once per workgroup: the hybrid of atomics and
+                               private copies that Sec. 7 proposes for short modes; only when
+                               I_n x lanes x columns x 4 (8 for FP64) bytes plus 4-8 KiB of
+                               staging fit 64 KiB of LDS (SPT_EUNSUPPORTED otherwise) */
 } spt_algo;
 
 /* Launch parameters of one MTTKRP.  Zero fields take the default.  A lane group of
@@ -70,7 +75,16 @@ typedef struct spt_tune {
     int32_t lanes_per_nnz;
     int32_t cols_per_lane;
     int32_t nnz_per_wave;
+    int32_t flags;  /* SPT_TUNE_DETERMINISTIC: see below */
 } spt_tune;
+
+/* spt_tune.flags.  SPT_TUNE_DETERMINISTIC (permuted algorithms only): the rows a wave chunk
+ * shares with its neighbours are not added atomically but parked in two scratch slots per chunk
+ * and summed by a second pass in sorted order, so the MTTKRP issues no atomic instruction and V
+ * is bit-reproducible from run to run (Sec. 5 notes that the segmented reduction can make
+ * atomics unnecessary).  The slots live in the tensor's radix-sort scratch: do not overlap with
+ * spt_tensor_permute or another deterministic MTTKRP on the same tensor. */
+#define SPT_TUNE_DETERMINISTIC 1
 
 typedef struct spt_tensor spt_tensor;
 

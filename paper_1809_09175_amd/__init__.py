@@ -10,8 +10,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (ALGO_ATOMIC, ALGO_AUTO, ALGO_PERMUTED, ALGO_PERMUTED_COPY, SPT_BF16, SPT_F32,
-                   SPT_F64, SptError, SptTune, SptUnavailable)
+from ._lib import (ALGO_ATOMIC, ALGO_AUTO, ALGO_PERMUTED, ALGO_PERMUTED_COPY, ALGO_PRIVATIZED,
+                   SPT_BF16, SPT_F32, SPT_F64, SptError, SptTune, SptUnavailable)
 
 __all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPPoissonLoss",
            "default_tune", "autotune", "Batch", "to_bf16", "stream_triad", "SptError",
@@ -19,10 +19,11 @@ __all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPPo
            "ALGO_AUTO", "ALGO_ATOMIC", "ALGO_PERMUTED", "dtype_code"]
 
 _ALGOS = {"auto": ALGO_AUTO, "atomic": ALGO_ATOMIC, "permuted": ALGO_PERMUTED,
-          "permuted_copy": ALGO_PERMUTED_COPY, ALGO_AUTO: ALGO_AUTO, ALGO_ATOMIC: ALGO_ATOMIC,
-          ALGO_PERMUTED: ALGO_PERMUTED, ALGO_PERMUTED_COPY: ALGO_PERMUTED_COPY}
+          "permuted_copy": ALGO_PERMUTED_COPY, "privatized": ALGO_PRIVATIZED,
+          ALGO_AUTO: ALGO_AUTO, ALGO_ATOMIC: ALGO_ATOMIC, ALGO_PERMUTED: ALGO_PERMUTED,
+          ALGO_PERMUTED_COPY: ALGO_PERMUTED_COPY, ALGO_PRIVATIZED: ALGO_PRIVATIZED}
 _ALGO_NAMES = {ALGO_AUTO: "auto", ALGO_ATOMIC: "atomic", ALGO_PERMUTED: "permuted",
-               ALGO_PERMUTED_COPY: "permuted_copy"}
+               ALGO_PERMUTED_COPY: "permuted_copy", ALGO_PRIVATIZED: "privatized"}
 
 
 def _stream(stream=None):
@@ -47,8 +48,9 @@ def _dev_check(t, name):
         raise ValueError(f"{name} must be a contiguous CUDA (HIP) tensor")
 
 
-def _tune(algo="auto", lanes=0, cols=0, chunk=0):
-    return SptTune(_ALGOS[algo], int(lanes), int(cols), int(chunk))
+def _tune(algo="auto", lanes=0, cols=0, chunk=0, deterministic=False):
+    return SptTune(_ALGOS[algo], int(lanes), int(cols), int(chunk),
+                   _lib.TUNE_DETERMINISTIC if deterministic else 0)
 
 
 class SparseTensor:
@@ -169,7 +171,7 @@ def _factor_ptrs(factors, skip=-1):
 
 
 def mttkrp(X: SparseTensor, factors, mode: int, lam=None, algo="auto", lanes=0, cols=0,
-           chunk=0, vals=None, out=None, stream=None):
+           chunk=0, vals=None, out=None, deterministic=False, stream=None):
     """Mode-`mode` MTTKRP (eq. (mttkrp)).  factors: d CUDA tensors (I_m, R) of one dtype
     (float64, float32 or bfloat16); lam: optional (R,) float64.  Returns V (I_n, R): float64
     for float64 factors, float32 otherwise."""
@@ -187,7 +189,7 @@ def mttkrp(X: SparseTensor, factors, mode: int, lam=None, algo="auto", lanes=0, 
             raise ValueError("lam must be float64")
     if vals is not None:
         _dev_check(vals, "vals")
-    tune = _tune(algo, lanes, cols, chunk)
+    tune = _tune(algo, lanes, cols, chunk, deterministic)
     _lib.check(lib.spt_mttkrp(X.handle, int(mode), R, _factor_ptrs(factors, mode), fd,
                               ctypes.c_void_p(lam.data_ptr()) if lam is not None else None,
                               ctypes.c_void_p(vals.data_ptr()) if vals is not None else None,

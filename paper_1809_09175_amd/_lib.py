@@ -15,7 +15,7 @@ SPT_OK, SPT_EINVAL, SPT_ERANGE, SPT_EHIP, SPT_ESINGULAR = 0, -1, -2, -3, -4
 SPT_EWORKSPACE, SPT_EUNSUPPORTED, SPT_ESTATE = -5, -6, -7
 SPT_F64, SPT_F32, SPT_BF16 = 0, 1, 2
 TUNE_BATCH_CONFIGS, TUNE_NO_ATOMIC, TUNE_NO_PERMUTED = 1, 2, 4
-ALGO_AUTO, ALGO_ATOMIC, ALGO_PERMUTED, ALGO_PERMUTED_COPY = 0, 1, 2, 3
+ALGO_AUTO, ALGO_ATOMIC, ALGO_PERMUTED, ALGO_PERMUTED_COPY, ALGO_PRIVATIZED = 0, 1, 2, 3, 4
 
 _c_p = ctypes.c_void_p
 _c_i = ctypes.c_int
@@ -26,7 +26,11 @@ _c_d = ctypes.c_double
 
 class SptTune(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("lanes_per_nnz", ctypes.c_int32),
-                ("cols_per_lane", ctypes.c_int32), ("nnz_per_wave", ctypes.c_int32)]
+                ("cols_per_lane", ctypes.c_int32), ("nnz_per_wave", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+TUNE_DETERMINISTIC = 1
 
 
 # name -> (restype, argtypes); every symbol include/spt.h declares

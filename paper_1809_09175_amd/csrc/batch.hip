@@ -63,7 +63,7 @@ __device__ __forceinline__ void batch_unit(int4 *smem4, const BatchItem &it, int
                                                          it.R, A, nullptr, nullptr, V, it.chunk, c0);
     } else {
         atomic_block_unit<D, G, CPL, FT, float, float>(smem4, it.rec, it.P, it.n, it.R, A, nullptr,
-                                                       nullptr, V, it.chunk, it.hbits, bc0);
+                                                       nullptr, V, it.chunk, it.hbits, 0, bc0);
     }
 }
 
@@ -192,6 +192,7 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         if (rc) return rc;
         if (t.algo == SPT_ALGO_PERMUTED && !X->permuted[n]) return SPT_ESTATE;
         if (t.algo == SPT_ALGO_PERMUTED_COPY && X->srec[n] == nullptr) return SPT_ESTATE;
+        if (t.flags & SPT_TUNE_DETERMINISTIC) return SPT_EUNSUPPORTED;
         const int kalgo = (t.algo == SPT_ALGO_PERMUTED_COPY) ? SPT_ALGO_PERMUTED : t.algo;
         const int cfg = batch_cfg_index(kalgo, X->d, t.lanes_per_nnz, t.cols_per_lane);
         if (cfg < 0) return SPT_EUNSUPPORTED;

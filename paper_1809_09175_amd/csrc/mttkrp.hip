@@ -38,6 +38,20 @@ static bool cfg_supported(int G, int CPL) {
     }
 }
 
+constexpr size_t kPrivatizedLds = 64 * 1024;
+
+static int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 256;
+    }
+    return cus;
+}
+
 static int pow2_at_least(int x) {
     int p = 1;
     while (p < x) p <<= 1;
@@ -102,14 +116,15 @@ static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out
 
 int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tune *in,
                  spt_tune *out) {
-    spt_tune t = in ? *in : spt_tune{0, 0, 0, 0};
+    spt_tune t = in ? *in : spt_tune{0, 0, 0, 0, 0};
     if (t.algo == SPT_ALGO_AUTO)
         t.algo = X->srec[mode] != nullptr ? SPT_ALGO_PERMUTED_COPY
                                           : (X->permuted[mode] ? SPT_ALGO_PERMUTED : SPT_ALGO_ATOMIC);
     if (t.algo != SPT_ALGO_ATOMIC && t.algo != SPT_ALGO_PERMUTED &&
-        t.algo != SPT_ALGO_PERMUTED_COPY)
+        t.algo != SPT_ALGO_PERMUTED_COPY && t.algo != SPT_ALGO_PRIVATIZED)
         return SPT_EINVAL;
-    const int lalgo = (t.algo == SPT_ALGO_ATOMIC) ? SPT_ALGO_ATOMIC : SPT_ALGO_PERMUTED;
+    const int lalgo = (t.algo == SPT_ALGO_ATOMIC || t.algo == SPT_ALGO_PRIVATIZED)
+                          ? SPT_ALGO_ATOMIC : SPT_ALGO_PERMUTED;
     int G = t.lanes_per_nnz, cpl = t.cols_per_lane;
     if (G == 0 && cpl == 0) {
         default_layout(R, fdtype, lalgo, &G, &cpl);
@@ -132,6 +147,14 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
     }
     if (t.nnz_per_wave < 64 || t.nnz_per_wave % 64 != 0 || t.nnz_per_wave > (1 << 20))
         return SPT_EINVAL;
+    if (t.algo == SPT_ALGO_PRIVATIZED) {
+        // the whole output must fit one workgroup's LDS next to the record staging buffer,
+        // within 64 KiB so two workgroups share a CU
+        const size_t at = (fdtype == SPT_F64) ? 8 : 4;
+        const size_t need = (size_t)(kBlock / kWave) * kWave * (X->rec_words / 4) * 16 +
+                            (size_t)X->dims[mode] * G * cpl * at;
+        if (need > kPrivatizedLds) return SPT_EUNSUPPORTED;
+    }
     t.lanes_per_nnz = G;
     t.cols_per_lane = cpl;
     *out = t;
@@ -157,7 +180,37 @@ int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *facto
     a.V = V;
     a.chunk = t.nnz_per_wave;
     a.algo = t.algo;
+    a.slot_keys = nullptr;
+    a.slot_vals = nullptr;
+    a.In = (int)X->dims[mode];
     a.hbits = default_hbits(R, t.lanes_per_nnz, t.cols_per_lane, fdtype, X->rec_words / 4);
+    if (t.algo == SPT_ALGO_PRIVATIZED) {
+        // privatised output: about two workgroups per CU, each adding a long contiguous range
+        // into its LDS copy of V, so every row is flushed to HBM only once per workgroup
+        a.algo = SPT_ALGO_ATOMIC;
+        a.hbits = -1;
+        int64_t blocks = 2 * (int64_t)device_cus();
+        const int64_t minb = ceil_div(X->P, (int64_t)(kBlock / kWave) * 64);
+        if (blocks > minb) blocks = minb;
+        int64_t ch = ceil_div(ceil_div(X->P, blocks * (kBlock / kWave)), 64) * 64;
+        a.chunk = (int)(ch < 64 ? 64 : ch);
+    }
+    if ((t.flags & SPT_TUNE_DETERMINISTIC) &&
+        (t.algo == SPT_ALGO_PERMUTED || t.algo == SPT_ALGO_PERMUTED_COPY)) {
+        // the boundary slots live in the radix-sort scratch (two P-entry int32 arrays), free
+        // once the permutations exist; chunks are lengthened until they fit
+        const size_t avail = 2 * align256((size_t)X->P * 4);
+        int64_t chunk = a.chunk;
+        for (;;) {
+            const int64_t ns = 2 * ceil_div(X->P, chunk);
+            if (align256((size_t)ns * 4) + (size_t)ns * R * at_bytes <= avail) break;
+            chunk *= 2;
+        }
+        a.chunk = (int)chunk;
+        const int64_t ns = 2 * ceil_div(X->P, chunk);
+        a.slot_keys = X->tmp_keys;
+        a.slot_vals = reinterpret_cast<uint8_t *>(X->tmp_keys) + align256((size_t)ns * 4);
+    }
     a.stream = s;
     switch (fdtype) {
         case SPT_F64: return launch_mttkrp_f64(a, X->d, factors, t.lanes_per_nnz, t.cols_per_lane);
@@ -220,7 +273,7 @@ extern "C" int spt_mttkrp_default_tune(const spt_tensor *X, int mode, int R, int
                                        int algo, spt_tune *out) {
     if (X == nullptr || out == nullptr || mode < 0 || mode >= X->d || R < 1 || R > 256)
         return SPT_EINVAL;
-    spt_tune in{algo, 0, 0, 0};
+    spt_tune in{algo, 0, 0, 0, 0};
     return resolve_tune(X, mode, R, fdtype, &in, out);
 }
 
@@ -265,10 +318,11 @@ extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
         return SPT_EHIP;
     }
     float bms = 1e30f;
-    spt_tune bt{0, 0, 0, 0};
+    spt_tune bt{0, 0, 0, 0, 0};
     int tried = 0;
     rc = SPT_OK;
-    for (int algo = SPT_ALGO_ATOMIC; algo <= SPT_ALGO_PERMUTED_COPY && rc == SPT_OK; ++algo) {
+    for (int algo = SPT_ALGO_ATOMIC; algo <= SPT_ALGO_PRIVATIZED && rc == SPT_OK; ++algo) {
+        if (algo == SPT_ALGO_PRIVATIZED && (batch_only || (flags & SPT_TUNE_NO_ATOMIC))) continue;
         if (algo == SPT_ALGO_PERMUTED && (!X->permuted[mode] || (flags & SPT_TUNE_NO_PERMUTED)))
             continue;
         if (algo == SPT_ALGO_PERMUTED_COPY &&
@@ -284,7 +338,8 @@ extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
             const int lalgo = (algo == SPT_ALGO_ATOMIC) ? SPT_ALGO_ATOMIC : SPT_ALGO_PERMUTED;
             (void)lalgo;
             for (int chunk : chunks) {
-                spt_tune t{algo, G, CPL, chunk}, r;
+                if (algo == SPT_ALGO_PRIVATIZED && chunk != chunks[0]) break;  // chunk is derived
+                spt_tune t{algo, G, CPL, chunk, 0}, r;
                 if (resolve_tune(X, mode, R, fdtype, &t, &r) != SPT_OK) continue;
                 rc = launch_mttkrp(X, mode, R, factors, fdtype, nullptr, nullptr, V, r, s);
                 if (rc) break;

@@ -178,7 +178,7 @@ __device__ __forceinline__ void lds_record(const int4 *q, int *w) {
 // while the registers still allow 6-8 waves per SIMD
 template <int CPL, int G>
 struct UnrollFor {
-    static constexpr int raw = 16 / CPL;
+    static constexpr int raw = 32 / CPL;
     static constexpr int value = raw < G ? raw : G;
 };
 
@@ -201,7 +201,9 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                                                 int n, int R, const FactorSet<FT> &A,
                                                 const double *__restrict__ lambda,
                                                 const VT *__restrict__ vovr, AT *__restrict__ V,
-                                                int chunk, int64_t c0) {
+                                                int chunk, int64_t c0,
+                                                int *__restrict__ slot_keys = nullptr,
+                                                AT *__restrict__ slot_vals = nullptr) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int NG = kWave / G;
     constexpr int U = UnrollFor<CPL, G>::value;
@@ -336,6 +338,11 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
     }
     wave_sync();
     if (g == 0) {
+        // Rows shared with neighbouring chunks are the chunk's first and last rows.  They are
+        // added atomically, or, in the deterministic mode, parked in two scratch slots per chunk
+        // (slot 2c: first row, slot 2c+1: last row or key -1) for k_det_fixup to sum in chunk
+        // order, so no atomic is issued at all.
+        const int64_t cid = c0 / chunk;
         int ck = -1;
         bool first_seg = true;
         AT cacc[CPL];
@@ -345,11 +352,19 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
             const int ke = sm.pkey[e];
             if (ke < 0) continue;
             if (ke != ck) {
-                if (ck >= 0 && colok) {
-                    if (first_seg) atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
-                    else store_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+                if (ck >= 0) {
+                    if (first_seg) {
+                        if (slot_keys != nullptr) {
+                            if (gl == 0) slot_keys[2 * cid] = ck;
+                            if (colok) store_cols<AT, CPL>(slot_vals + 2 * cid * R + col0, cacc);
+                        } else if (colok) {
+                            atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+                        }
+                    } else if (colok) {
+                        store_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+                    }
+                    first_seg = false;
                 }
-                if (ck >= 0) first_seg = false;
                 ck = ke;
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) cacc[c] = 0;
@@ -357,7 +372,47 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
 #pragma unroll
             for (int c = 0; c < CPL; ++c) cacc[c] += sm.part[e][col0 + c];
         }
-        if (ck >= 0 && colok) atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+        if (ck >= 0) {
+            if (slot_keys != nullptr) {
+                const int64_t slot = first_seg ? 2 * cid : 2 * cid + 1;
+                if (gl == 0) {
+                    slot_keys[slot] = ck;
+                    if (first_seg) slot_keys[2 * cid + 1] = -1;
+                }
+                if (colok) store_cols<AT, CPL>(slot_vals + slot * R + col0, cacc);
+            } else if (colok) {
+                atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
+            }
+        }
+    }
+}
+
+// Deterministic mode, second pass: one wavefront per slot; the first slot of every run of equal
+// keys sums the run in slot (= sorted) order and stores the row.  Slots with key -1 are skipped.
+template <class AT>
+__global__ __launch_bounds__(kBlock) void k_det_fixup(const int *__restrict__ keys,
+                                                      const AT *__restrict__ vals,
+                                                      int64_t nslots, int R,
+                                                      AT *__restrict__ V) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    if (i >= nslots) return;
+    const int k = keys[i];
+    if (k < 0) return;
+    if (i > 0) {
+        int prev = keys[i - 1];
+        if (prev < 0 && i > 1) prev = keys[i - 2];
+        if (prev == k) return;  // not the first slot of its run
+    }
+    for (int col = lane; col < R; col += kWave) {
+        AT s = 0;
+        for (int64_t j = i; j < nslots; ++j) {
+            const int kj = keys[j];
+            if (kj < 0) continue;
+            if (kj != k) break;
+            s += vals[j * R + col];
+        }
+        V[(int64_t)k * R + col] = s;
     }
 }
 
@@ -366,13 +421,13 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
     const int4 *__restrict__ rec, const int32_t *__restrict__ perm,
     const int4 *__restrict__ srec, int64_t P, int n, int R,
     FactorSet<FT> A, const double *__restrict__ lambda, const VT *__restrict__ vovr,
-    AT *__restrict__ V, int chunk) {
+    AT *__restrict__ V, int chunk, int *__restrict__ slot_keys, AT *__restrict__ slot_vals) {
     __shared__ PermShared<D, G, CPL, VT, AT> sm[kBlock / kWave];
     const int wave = threadIdx.x >> 6;
     const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
     if (c0 >= P) return;  // whole wavefront leaves together
     perm_wave_chunk<D, G, CPL, FT, VT, AT>(sm[wave], rec, perm, srec, P, n, R, A, lambda, vovr, V,
-                                           chunk, c0);
+                                           chunk, c0, slot_keys, slot_vals);
 }
 
 // One workgroup processes storage positions [bc0, bc0 + 4 chunk) (one chunk per wavefront)
@@ -383,21 +438,26 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
                                                   const double *__restrict__ lambda,
                                                   const VT *__restrict__ vovr,
                                                   AT *__restrict__ V, int chunk, int hbits,
+                                                  int In,
                                                   int64_t bc0) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int RP = G * CPL;
     constexpr int U = UnrollFor<CPL, G>::value;
     int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
+    // hbits > 0: hash table of 2^hbits rows; hbits == 0: no table; hbits < 0: "privatised"
+    // output, one LDS row per output row k < In (slot = k, no keys)
+    const bool direct = hbits < 0;
     int *hkeys = reinterpret_cast<int *>(smem4 + (kBlock / kWave) * kWave * RQ);
-    const int H = hbits > 0 ? (1 << hbits) : 0;
-    AT *hvals = reinterpret_cast<AT *>(hkeys + (H > 2 ? H : 2));
+    const int H = direct ? In : (hbits > 0 ? (1 << hbits) : 0);
+    AT *hvals = direct ? reinterpret_cast<AT *>(hkeys) : reinterpret_cast<AT *>(hkeys + (H > 2 ? H : 2));
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
     const bool colok = col0 < R;
     const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
-    for (int i = tid; i < H; i += kBlock) hkeys[i] = -1;
+    if (!direct)
+        for (int i = tid; i < H; i += kBlock) hkeys[i] = -1;
     for (int i = tid; i < H * RP; i += kBlock) hvals[i] = 0;
     __syncthreads();
 
@@ -440,8 +500,8 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
             for (int u = 0; u < U; ++u) {
                 const int k = kk[u];
                 if (k < 0) continue;
-                int slot = -1;
-                if (H > 0) {
+                int slot = direct ? k : -1;
+                if (!direct && H > 0) {
                     uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - hbits);
                     for (int probe = 0; probe < 4; ++probe) {
                         int cur = __hip_atomic_load(&hkeys[h], __ATOMIC_RELAXED,
@@ -475,8 +535,13 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
     __syncthreads();
     for (int i = tid; i < H * RP; i += kBlock) {
         const int slot = i / RP, col = i - slot * RP;
-        const int k = hkeys[slot];
-        if (k >= 0 && col < R) atomic_add_f(V + (int64_t)k * R + col, hvals[i]);
+        if (direct) {
+            // skip untouched entries: adding zero changes nothing
+            if (col < R && hvals[i] != (AT)0) atomic_add_f(V + (int64_t)slot * R + col, hvals[i]);
+        } else {
+            const int k = hkeys[slot];
+            if (k >= 0 && col < R) atomic_add_f(V + (int64_t)k * R + col, hvals[i]);
+        }
     }
 }
 
@@ -484,9 +549,9 @@ template <int D, int G, int CPL, class FT, class VT, class AT>
 __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
     const int4 *__restrict__ rec, int64_t P, int n, int R, FactorSet<FT> A,
     const double *__restrict__ lambda, const VT *__restrict__ vovr, AT *__restrict__ V,
-    int chunk, int hbits) {
+    int chunk, int hbits, int In) {
     extern __shared__ int4 smem4[];
-    atomic_block_unit<D, G, CPL, FT, VT, AT>(smem4, rec, P, n, R, A, lambda, vovr, V, chunk, hbits,
+    atomic_block_unit<D, G, CPL, FT, VT, AT>(smem4, rec, P, n, R, A, lambda, vovr, V, chunk, hbits, In,
                                              (int64_t)blockIdx.x * (kBlock / kWave) * chunk);
 }
 
@@ -506,6 +571,9 @@ struct MttkrpArgs {
     int chunk;
     int hbits;
     int algo;
+    int *slot_keys;   // deterministic mode: 2 slots per wave chunk (null: boundary atomics)
+    void *slot_vals;
+    int In;           // output rows (privatised mode: hbits < 0)
     hipStream_t stream;
 };
 
@@ -513,6 +581,11 @@ template <class AT>
 inline size_t atomic_smem_bytes(int RQ, int H, int RP) {
     return (size_t)(kBlock / kWave) * kWave * RQ * 16 + (size_t)(H > 2 ? H : 2) * 4 +
            (size_t)H * RP * sizeof(AT);
+}
+
+template <class AT>
+inline size_t privatized_smem_bytes(int RQ, int In, int RP) {
+    return (size_t)(kBlock / kWave) * kWave * RQ * 16 + (size_t)In * RP * sizeof(AT);
 }
 
 template <int D, int G, int CPL, class FT, class VT, class AT>
@@ -525,13 +598,20 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
     if (a.algo == SPT_ALGO_PERMUTED || a.algo == SPT_ALGO_PERMUTED_COPY) {
         hipLaunchKernelGGL((k_mttkrp_perm<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock), 0,
                            a.stream, a.rec, a.perm, a.srec, a.P, a.n, a.R, A, a.lambda, vovr, V,
-                           a.chunk);
+                           a.chunk, a.slot_keys, static_cast<AT *>(a.slot_vals));
+        if (a.slot_keys != nullptr) {
+            const int64_t nslots = 2 * ceil_div(a.P, a.chunk);
+            hipLaunchKernelGGL((k_det_fixup<AT>), dim3((unsigned)ceil_div(nslots, kBlock / kWave)),
+                               dim3(kBlock), 0, a.stream, a.slot_keys,
+                               static_cast<const AT *>(a.slot_vals), nslots, a.R, V);
+        }
     } else {
         const int H = a.hbits > 0 ? (1 << a.hbits) : 0;
-        const size_t smem = atomic_smem_bytes<AT>(RecShape<D, VT>::RQ, H, G * CPL);
+        const size_t smem = a.hbits < 0 ? privatized_smem_bytes<AT>(RecShape<D, VT>::RQ, a.In, G * CPL)
+                                        : atomic_smem_bytes<AT>(RecShape<D, VT>::RQ, H, G * CPL);
         hipLaunchKernelGGL((k_mttkrp_atomic<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock),
                            smem, a.stream, a.rec, a.P, a.n, a.R, A, a.lambda, vovr, V, a.chunk,
-                           a.hbits);
+                           a.hbits, a.In);
     }
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }

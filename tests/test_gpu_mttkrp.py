@@ -297,3 +297,51 @@ def test_sorted_copy_matches_gathered(gpu, kind, R, d):
     with pytest.raises(SptError) as e:
         spt.mttkrp(T, dev, 0, algo="permuted_copy")
     assert e.value.code == -7
+
+
+@pytest.mark.parametrize("kind,R,chunk", [("f32", 32, 64), ("f32", 16, 0), ("bf16", 32, 256),
+                                          ("f64", 16, 64), ("f64", 256, 64)])
+def test_deterministic_permuted_is_reproducible_and_atomic_free(gpu, kind, R, chunk):
+    """Deterministic mode: chunk-boundary rows go to scratch slots summed in sorted order, so
+    two runs give bit-identical V; matches the oracle and the atomic-boundary kernel."""
+    import paper_1809_09175_amd as spt
+    dims = (600, 500, 40)
+    X = _small(kind, dims, 80_003, (1.1, 1.1, 1.1), seed=19)
+    T = _dev_tensor(X, np.float64 if kind == "f64" else np.float32)
+    T.permute()
+    T.sort_copy(1)
+    dev, ref = _factors(dims, R, seed=7, kind=kind)
+    lam = torch.from_numpy(np.linspace(0.5, 2.0, R)).cuda()
+    y = torch.from_numpy(np.random.default_rng(3).standard_normal(X.nnz).astype(
+        np.float64 if kind == "f64" else np.float32)).cuda()
+    for n in range(3):
+        V_ref = oracle.mttkrp(X.subs, X.vals, dims, ref, n, lam.cpu().numpy())
+        for vals in (None, y):
+            a = spt.mttkrp(T, dev, n, lam=lam, vals=vals, chunk=chunk, deterministic=True)
+            b = spt.mttkrp(T, dev, n, lam=lam, vals=vals, chunk=chunk, deterministic=True)
+            c = spt.mttkrp(T, dev, n, lam=lam, vals=vals, chunk=chunk)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b), n
+            tight = 1e-14 if kind == "f64" else 1e-6
+            assert _relerr(a.cpu().numpy(), c.cpu().numpy().astype(np.float64)) < tight
+            if vals is None:
+                assert _relerr(a.cpu().numpy(), V_ref) < TOL[kind]
+
+
+def test_privatized_short_mode(gpu):
+    """Privatised output for short modes (whole V in one workgroup's LDS): parity, and the
+    eligibility check rejects long modes."""
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import SptError
+    dims = (5000, 365, 40, 7)
+    X = _small("f32", dims, 120_007, (1.2, 0.0, 1.1, 0.0), seed=23)
+    T = _dev_tensor(X, np.float32)
+    for R in (8, 16, 32):
+        dev, ref = _factors(dims, R, seed=R, kind="f32")
+        for n in (1, 2, 3):
+            V = spt.mttkrp(T, dev, n, algo="privatized")
+            torch.cuda.synchronize()
+            assert _relerr(V.cpu().numpy(), oracle.mttkrp(X.subs, X.vals, dims, ref, n)) < 1e-5
+        with pytest.raises(SptError) as e:
+            spt.mttkrp(T, dev, 0, algo="privatized")
+        assert e.value.code == -6
