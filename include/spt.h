@@ -279,6 +279,19 @@ int spt_gcp_poisson_backward(const spt_tensor *X, int R, const void *const *fact
                              const void *w, const void *m, const double *gscale, void *y,
                              void *const *grads, const spt_tune *tune, void *stream);
 
+/* The same with a choice of elementwise loss (generalized CP for count, binary and real data):
+ *   SPT_GCP_POISSON   f = exp(m) - x m,            df/dm = exp(m) - x
+ *   SPT_GCP_BERNOULLI f = log(1 + exp(m)) - x m,   df/dm = 1 / (1 + exp(-m)) - x
+ *   SPT_GCP_GAUSSIAN  f = (x - m)^2,               df/dm = 2 (m - x)
+ * Arguments as for the Poisson calls; loss_kind outside these values gives SPT_EINVAL. */
+enum { SPT_GCP_POISSON = 0, SPT_GCP_BERNOULLI = 1, SPT_GCP_GAUSSIAN = 2 };
+int spt_gcp_forward(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                    int loss_kind, const void *w, void *m, double *loss, void *ws,
+                    size_t ws_bytes, void *stream);
+int spt_gcp_backward(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                     int loss_kind, const void *w, const void *m, const double *gscale, void *y,
+                     void *const *grads, const spt_tune *tune, void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Precision and measurement helpers
  * ------------------------------------------------------------------------------------------- */

@@ -17,6 +17,8 @@ Functions and what pins them (tests/test_oracle_pins.py):
   cp_als_mode   Sec. 3 (textbook ALS)  -- normal-equation optimality, independent lstsq ALS,
                                           exact low-rank recovery, monotone fit
   gcp_poisson   Sec. 7 (future work: generalized CP) -- central finite differences, dense loss
+  gcp           the same with Bernoulli-logit and Gaussian losses -- finite differences, dense
+                loss, Gaussian gradient = 2 (model - data) MTTKRP closed form
   bf16_rne      rounding of FP32 to BF16 -- torch's CPU conversion on sampled and boundary bits
 """
 from __future__ import annotations
@@ -185,6 +187,27 @@ def gcp_poisson(subs, vals, dims, factors, w=None, grads=True):
     _check(_load().oracle_gcp_poisson(*t.head(), _p(t.vals), _p(w), ctypes.c_int(R), arr,
                                       ctypes.byref(loss), garr))
     return (loss.value, gs) if grads else loss.value
+
+
+GCP_LOSSES = {"poisson": 0, "bernoulli": 1, "gaussian": 2}
+
+
+def gcp(subs, vals, dims, factors, loss="poisson", w=None, grads=True):
+    """Generalized CP loss (poisson: exp(m) - x m; bernoulli: log(1+exp(m)) - x m; gaussian:
+    (x - m)^2) over the stored entries, and its gradient (an MTTKRP per mode)."""
+    t = _T(subs, vals, dims)
+    R = int(np.asarray(factors[0]).shape[1])
+    fs, arr = _factor_array(factors, t.dims, R)
+    w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    out = ctypes.c_double()
+    gs = None
+    garr = None
+    if grads:
+        gs = [np.empty((int(t.dims[m]), R), dtype=np.float64) for m in range(t.d)]
+        garr = (ctypes.c_void_p * t.d)(*[g.ctypes.data for g in gs])
+    _check(_load().oracle_gcp(*t.head(), _p(t.vals), _p(w), ctypes.c_int(R), arr,
+                              ctypes.c_int(GCP_LOSSES[loss]), ctypes.byref(out), garr))
+    return (out.value, gs) if grads else out.value
 
 
 def bf16_rne(x):

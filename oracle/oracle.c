@@ -251,13 +251,34 @@ done:
     return rc;
 }
 
-int oracle_gcp_poisson(int d, const int64_t *dims, int64_t P, const int32_t *subs,
-                       const double *vals, const double *w, int R, const double *const *A,
-                       double *loss, double *const *grads)
+/* elementwise loss and derivative of the generalized CP losses (plain definitions) */
+static double gcp_f(int kind, double x, double m)
+{
+    switch (kind) {
+    case 0: return exp(m) - x * m;
+    case 1: return log1p(exp(m)) - x * m;
+    default: return (x - m) * (x - m);
+    }
+}
+
+static double gcp_df(int kind, double x, double m)
+{
+    switch (kind) {
+    case 0: return exp(m) - x;
+    case 1: return 1.0 / (1.0 + exp(-m)) - x;
+    default: return 2.0 * (m - x);
+    }
+}
+
+int oracle_gcp(int d, const int64_t *dims, int64_t P, const int32_t *subs, const double *vals,
+               const double *w, int R, const double *const *A, int loss_kind, double *loss,
+               double *const *grads)
 {
     int rc = check_tensor(d, dims, P, subs);
     if (rc) return rc;
-    if (R < 1 || A == NULL || loss == NULL || (P > 0 && vals == NULL)) return ORACLE_EINVAL;
+    if (R < 1 || A == NULL || loss == NULL || (P > 0 && vals == NULL) || loss_kind < 0 ||
+        loss_kind > 2)
+        return ORACLE_EINVAL;
     double *m = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
     double *y = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
     rc = ORACLE_EINVAL;
@@ -267,8 +288,8 @@ int oracle_gcp_poisson(int d, const int64_t *dims, int64_t P, const int32_t *sub
     double L = 0.0;
     for (int64_t i = 0; i < P; ++i) {
         double wi = w ? w[i] : 1.0;
-        L += wi * (exp(m[i]) - vals[i] * m[i]);
-        y[i] = wi * (exp(m[i]) - vals[i]);
+        L += wi * gcp_f(loss_kind, vals[i], m[i]);
+        y[i] = wi * gcp_df(loss_kind, vals[i], m[i]);
     }
     *loss = L;
     if (grads)
@@ -278,6 +299,13 @@ done:
     free(m);
     free(y);
     return rc;
+}
+
+int oracle_gcp_poisson(int d, const int64_t *dims, int64_t P, const int32_t *subs,
+                       const double *vals, const double *w, int R, const double *const *A,
+                       double *loss, double *const *grads)
+{
+    return oracle_gcp(d, dims, P, subs, vals, w, R, A, 0, loss, grads);
 }
 
 static double bits_to_float_as_double(uint32_t b)

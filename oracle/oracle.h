@@ -73,6 +73,15 @@ int oracle_gcp_poisson(int d, const int64_t *dims, int64_t P, const int32_t *sub
                        const double *vals, const double *w, int R, const double *const *A,
                        double *loss, double *const *grads);
 
+/* Generalized CP with a choice of elementwise loss f(x, m) and its derivative df/dm:
+ *   loss 0, Poisson with log link:  f = exp(m) - x m,          df = exp(m) - x
+ *   loss 1, Bernoulli with logit:   f = log(1 + exp(m)) - x m,  df = 1 / (1 + exp(-m)) - x
+ *   loss 2, Gaussian:               f = (x - m)^2,              df = 2 (m - x)
+ * loss = sum_i w_i f(x_i, m_i), grad[n] = MTTKRP(Y, A, n) with y_i = w_i df(x_i, m_i). */
+int oracle_gcp(int d, const int64_t *dims, int64_t P, const int32_t *subs, const double *vals,
+               const double *w, int R, const double *const *A, int loss_kind, double *loss,
+               double *const *grads);
+
 /* FP32 -> BF16 round to nearest, ties to even, by comparing the distances to the two
  * neighbouring BF16 values.  NaN maps to a quiet NaN with the same sign and top payload. */
 uint16_t oracle_bf16_rne(uint32_t f32_bits);

@@ -13,7 +13,8 @@ from . import _lib
 from ._lib import (ALGO_ATOMIC, ALGO_AUTO, ALGO_PERMUTED, ALGO_PERMUTED_COPY, ALGO_PRIVATIZED,
                    SPT_BF16, SPT_F32, SPT_F64, SptError, SptTune, SptUnavailable)
 
-__all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPPoissonLoss",
+__all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPLoss",
+           "GCPPoissonLoss",
            "default_tune", "autotune", "Batch", "to_bf16", "stream_triad", "SptError",
            "SptUnavailable",
            "ALGO_AUTO", "ALGO_ATOMIC", "ALGO_PERMUTED", "dtype_code"]
@@ -302,33 +303,39 @@ def model_values(X: SparseTensor, factors, lam=None, stream=None):
 
 # ----------------------------------------------------------------------- generalized CP (GCP)
 
-class GCPPoissonLoss(torch.autograd.Function):
-    """loss = sum_i w_i (exp(m_i) - x_i m_i) over the tensor's stored entries (nonzeros and
-    sampled zeros), m_i = sum_j prod_m A^(m)(l_im, j).  Forward and backward run in libspt; the
-    backward is one MTTKRP per mode of the derivative tensor y_i = w_i (exp(m_i) - x_i).
+class GCPLoss(torch.autograd.Function):
+    """Generalized CP loss sum_i w_i f(x_i, m_i) over the tensor's stored entries (nonzeros and
+    sampled zeros), m_i = sum_j prod_m A^(m)(l_im, j), with f one of
+      "poisson"   exp(m) - x m         (count data, log link)
+      "bernoulli" log(1 + exp(m)) - x m (binary data, logit link)
+      "gaussian"  (x - m)^2
+    Forward and backward run in libspt; the backward is one MTTKRP per mode of the derivative
+    tensor y_i = w_i df/dm(x_i, m_i).
 
-    Usage: loss = GCPPoissonLoss.apply(X, w, *factors)   (w may be None)."""
+    Usage: loss = GCPLoss.apply(X, w, "bernoulli", *factors)   (w may be None)."""
 
     @staticmethod
-    def forward(ctx, X, w, *factors):
+    def forward(ctx, X, w, loss_kind, *factors):
         lib = _lib.load()
         fd = dtype_code(factors[0])
         if fd == SPT_BF16:
             raise TypeError("GCP factors must be float32 or float64")
+        kind = _lib.GCP_LOSSES[loss_kind]
         R = int(factors[0].shape[1])
         vdt = torch.float64 if fd == SPT_F64 else torch.float32
         facs = [f.detach().contiguous() for f in factors]
         m = torch.empty(X.nnz, dtype=vdt, device=X.device)
         loss = torch.empty((), dtype=torch.float64, device=X.device)
         ws = torch.empty(32768, dtype=torch.uint8, device=X.device)
-        _lib.check(lib.spt_gcp_poisson_forward(
-            X.handle, R, _factor_ptrs(facs), fd,
+        _lib.check(lib.spt_gcp_forward(
+            X.handle, R, _factor_ptrs(facs), fd, kind,
             ctypes.c_void_p(w.data_ptr()) if w is not None else None,
             ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
-            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "spt_gcp_poisson_forward")
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()), "spt_gcp_forward")
         ctx.X = X
         ctx.w = w
         ctx.fd = fd
+        ctx.kind = kind
         ctx.save_for_backward(m, *facs)
         return loss
 
@@ -340,13 +347,26 @@ class GCPPoissonLoss(torch.autograd.Function):
         g = gout.detach().to(torch.float64).contiguous()
         y = torch.empty_like(m)
         grads = [torch.empty_like(f) for f in facs]
-        _lib.check(_lib.load().spt_gcp_poisson_backward(
-            X.handle, R, _factor_ptrs(facs), ctx.fd,
+        _lib.check(_lib.load().spt_gcp_backward(
+            X.handle, R, _factor_ptrs(facs), ctx.fd, ctx.kind,
             ctypes.c_void_p(ctx.w.data_ptr()) if ctx.w is not None else None,
             ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(g.data_ptr()),
             ctypes.c_void_p(y.data_ptr()), _lib.ptr_array([t.data_ptr() for t in grads]), None,
-            _stream()), "spt_gcp_poisson_backward")
-        return (None, None, *grads)
+            _stream()), "spt_gcp_backward")
+        return (None, None, None, *grads)
+
+
+class GCPPoissonLoss(torch.autograd.Function):
+    """The Poisson (log link) case of GCPLoss.  Usage: GCPPoissonLoss.apply(X, w, *factors)."""
+
+    @staticmethod
+    def forward(ctx, X, w, *factors):
+        return GCPLoss.forward(ctx, X, w, "poisson", *factors)
+
+    @staticmethod
+    def backward(ctx, gout):
+        g = GCPLoss.backward(ctx, gout)
+        return (g[0], g[1], *g[3:])
 
 
 # ------------------------------------------------------------------ autotuner and batching

@@ -31,6 +31,7 @@ class SptTune(ctypes.Structure):
 
 
 TUNE_DETERMINISTIC = 1
+GCP_LOSSES = {"poisson": 0, "bernoulli": 1, "gaussian": 2}
 
 
 # name -> (restype, argtypes); every symbol include/spt.h declares
@@ -70,6 +71,10 @@ SIGNATURES = {
     "spt_batch_launch": (_c_i, [_c_p, _c_p]),
     "spt_batch_info": (_c_i, [_c_p, _c_p, _c_p]),
     "spt_batch_destroy": (_c_i, [_c_p]),
+    "spt_gcp_forward": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_i, _c_p, _c_p, _c_p, _c_p, _c_sz,
+                               _c_p]),
+    "spt_gcp_backward": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p,
+                                _c_p, _c_p]),
     "spt_f32_to_bf16": (_c_i, [_c_p, _c_p, _c_i64, _c_p]),
     "spt_stream_triad": (_c_i, [_c_p, _c_p, _c_p, ctypes.c_float, _c_i64, _c_p]),
 }

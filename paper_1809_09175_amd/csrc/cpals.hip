@@ -242,11 +242,18 @@ __global__ void k_norms_from_gram(const double *__restrict__ GY, int R, double *
 // ------------------------------------------------------------------------------------------
 enum { KIND_FIT = 0, KIND_VALUES = 1, KIND_GCP = 2 };
 
+// generalized CP elementwise losses (FP64): 0 Poisson log link, 1 Bernoulli logit, 2 Gaussian
+__device__ __forceinline__ double gcp_loss_term(int loss, double x, double m) {
+    if (loss == 0) return exp(m) - x * m;
+    if (loss == 1) return (m > 0.0 ? m : 0.0) + log1p(exp(-fabs(m))) - x * m;  // log(1 + e^m)
+    return (x - m) * (x - m);
+}
+
 template <int D, int G, int CPL, class FT, class VT, class CT, int KIND>
 __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, int64_t P, int R,
                                                   FactorSet<FT> A, const double *__restrict__ lambda,
                                                   const CT *__restrict__ w, void *__restrict__ mout,
-                                                  double *__restrict__ part, int chunk) {
+                                                  double *__restrict__ part, int chunk, int loss) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int U = UnrollFor<CPL, G>::value;
     __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
@@ -322,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, 
                         } else {
                             static_cast<CT *>(mout)[i] = m;
                             const double wi = (w != nullptr) ? (double)w[i] : 1.0;
-                            s0acc += wi * (exp((double)m) - (double)x[u] * (double)m);
+                            s0acc += wi * gcp_loss_term(loss, (double)x[u], (double)m);
                         }
                     }
                 }
@@ -402,7 +409,7 @@ static void model_layout(int R, int *G, int *CPL) {
 template <int D, class FT, class VT, class CT, int KIND>
 static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
                           const double *lambda, const CT *w, void *mout, double *part,
-                          int *nblk_out, hipStream_t s) {
+                          int *nblk_out, hipStream_t s, int loss) {
     const int chunk = 2048;
     int64_t nchunks = ceil_div(X->P, chunk);
     int64_t nblk = ceil_div(nchunks, kBlock / kWave);
@@ -414,7 +421,8 @@ static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
 #define SPT_MODEL_CFG(GG, CC)                                                                  \
     case GG * 16 + CC:                                                                         \
         hipLaunchKernelGGL((k_model<D, GG, CC, FT, VT, CT, KIND>), dim3((unsigned)nblk),        \
-                           dim3(kBlock), 0, s, X->rec, X->P, R, A, lambda, w, mout, part, chunk); \
+                           dim3(kBlock), 0, s, X->rec, X->P, R, A, lambda, w, mout, part, chunk,  \
+                           loss);                                                              \
         break;
     switch (G * 16 + CPL) {
         SPT_MODEL_CFG(8, 1)
@@ -432,14 +440,14 @@ static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
 
 template <class FT, class VT, class CT, int KIND>
 int launch_model(const spt_tensor *X, int R, const void *const *factors, const double *lambda,
-                 const CT *w, void *mout, double *part, int *nblk, hipStream_t s) {
+                 const CT *w, void *mout, double *part, int *nblk, hipStream_t s, int loss = 0) {
     FactorSet<FT> A{};
     for (int m = 0; m < X->d; ++m) A.p[m] = static_cast<const FT *>(factors[m]);
     switch (X->d) {
-        case 2: return launch_model_d<2, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
-        case 3: return launch_model_d<3, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
-        case 4: return launch_model_d<4, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
-        case 5: return launch_model_d<5, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s);
+        case 2: return launch_model_d<2, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s, loss);
+        case 3: return launch_model_d<3, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s, loss);
+        case 4: return launch_model_d<4, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s, loss);
+        case 5: return launch_model_d<5, FT, VT, CT, KIND>(X, R, A, lambda, w, mout, part, nblk, s, loss);
         default: return SPT_EUNSUPPORTED;
     }
 }
@@ -645,15 +653,18 @@ int spt_model_values(const spt_tensor *X, int R, const void *const *factors, int
 // GCP forward reuses k_model; defined here so the loss reduction kernel stays local.
 namespace spt {
 int gcp_forward_impl(const spt_tensor *X, int R, const void *const *factors, int fdtype,
-                     const void *w, void *m, double *loss, double *part, hipStream_t s) {
+                     int loss_kind, const void *w, void *m, double *loss, double *part,
+                     hipStream_t s) {
     int nblk = 0;
     int rc;
     if (fdtype == SPT_F64)
         rc = launch_model<double, double, double, KIND_GCP>(X, R, factors, nullptr,
-                                                           static_cast<const double *>(w), m, part, &nblk, s);
+                                                           static_cast<const double *>(w), m, part,
+                                                           &nblk, s, loss_kind);
     else
         rc = launch_model<float, float, float, KIND_GCP>(X, R, factors, nullptr,
-                                                        static_cast<const float *>(w), m, part, &nblk, s);
+                                                        static_cast<const float *>(w), m, part,
+                                                        &nblk, s, loss_kind);
     if (rc) return rc;
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kBlock), 0, s, part, nblk, loss);
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;

@@ -217,3 +217,26 @@ def test_gcp_gradcheck_fp64(gpu):
     facs = tuple(torch.from_numpy(a.astype(np.float64)).cuda().requires_grad_(True) for a in A)
     assert torch.autograd.gradcheck(lambda *f: spt.GCPPoissonLoss.apply(T, None, *f), facs,
                                     eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+@pytest.mark.parametrize("loss", ["bernoulli", "gaussian", "poisson"])
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_gcp_general_losses(gpu, loss, kind):
+    import paper_1809_09175_amd as spt
+    dt = np.float64 if kind == "f64" else np.float32
+    X, A = _gcp_case(dt)
+    if loss == "bernoulli":
+        X.vals = (X.vals > 0).astype(dt)
+    T = _dev_tensor(X, dt)
+    T.permute()
+    rng = np.random.default_rng(4)
+    w = (rng.random(X.nnz) + 0.5).astype(dt)
+    facs = [torch.from_numpy(a - 0.2).cuda().requires_grad_(True) for a in A]
+    L = spt.GCPLoss.apply(T, torch.from_numpy(w).cuda(), loss, *facs)
+    (0.5 * L).backward()
+    L_ref, g_ref = oracle.gcp(X.subs, X.vals, X.dims, [a.astype(np.float64) - 0.2 for a in A],
+                              loss, w.astype(np.float64))
+    tol, gtol = (1e-12, 1e-12) if kind == "f64" else (1e-5, 1e-4)
+    assert abs(L.item() - L_ref) < tol * abs(L_ref)
+    for n in range(3):
+        assert _relerr(facs[n].grad.cpu().numpy(), 0.5 * g_ref[n]) < gtol, n

@@ -28,7 +28,10 @@ MUTANTS = [
      "        if (1)\n            for (int a = 0; a < R * R; ++a) Gam[a]"),
     ("norm not square-rooted", "lambda[j] = sqrt(s);", "lambda[j] = s;"),
     ("fit cross term", "double r2 = xx - 2.0 * xm + mm;", "double r2 = xx - xm + mm;"),
-    ("gcp derivative sign", "y[i] = wi * (exp(m[i]) - vals[i]);", "y[i] = wi * (exp(m[i]) + vals[i]);"),
+    ("gcp derivative sign", "case 0: return exp(m) - x;", "case 0: return exp(m) + x;"),
+    ("logit derivative", "case 1: return 1.0 / (1.0 + exp(-m)) - x;", "case 1: return 1.0 / (1.0 + exp(m)) - x;"),
+    ("gaussian derivative factor", "default: return 2.0 * (m - x);", "default: return (m - x);"),
+    ("gaussian loss sign", "default: return (x - m) * (x - m);", "default: return (x + m) * (x - m);"),
     ("unstable perm", "for (int64_t i = 0; i < P; ++i) {\n        int32_t k = subs[i * d + n];",
      "for (int64_t i = P - 1; i >= 0; --i) {\n        int32_t k = subs[i * d + n];"),
     ("bf16 ties away", "? hi_bits : lo_bits; /* tie", "? lo_bits : hi_bits; /* tie"),
@@ -44,6 +47,8 @@ CHECKS = [
     (pins.test_fit_matches_brute_force_residual, {}),
     (pins.test_cp_als_mode_solves_normal_equations_and_matches_lstsq, {}),
     (pins.test_gcp_poisson_loss_dense_and_gradient_finite_differences, {}),
+    (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="bernoulli")),
+    (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="gaussian")),
     (pins.test_bf16_rne_matches_torch_on_samples_and_boundaries, {}),
 ]
 

@@ -308,3 +308,36 @@ def test_bf16_rne_matches_torch_on_samples_and_boundaries():
     # largest finite FP32 rounds to infinity; the largest finite BF16 stays
     assert oracle.bf16_rne(np.array([0x7F7FFFFF], np.uint32))[0] == 0x7F80
     assert oracle.bf16_rne(np.array([0x7F7F0000], np.uint32))[0] == 0x7F7F
+
+
+@pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian"])
+def test_gcp_losses_dense_and_finite_differences(loss):
+    rng = np.random.default_rng(43)
+    dims = (5, 4, 3)
+    cells = rng.choice(int(np.prod(dims)), size=30, replace=False)
+    subs = np.stack(np.unravel_index(cells, dims), axis=1).astype(np.int32)
+    vals = (rng.random(30) < 0.5).astype(np.float64) if loss == "bernoulli" else rng.random(30) * 3
+    w = rng.random(30) + 0.5
+    R = 2
+    A = [rng.random((I, R)) - 0.3 for I in dims]
+    L, grads = oracle.gcp(subs, vals, dims, A, loss, w)
+    M = np.einsum("ir,jr,kr->ijk", *A)[subs[:, 0], subs[:, 1], subs[:, 2]]
+    f = {"poisson": np.exp(M) - vals * M, "bernoulli": np.logaddexp(0.0, M) - vals * M,
+         "gaussian": (vals - M) ** 2}[loss]
+    assert abs(L - np.sum(w * f)) < 1e-12 * abs(L)
+    if loss == "gaussian":
+        # d/dA of sum w (x - m)^2 = MTTKRP of 2 w (m - x): check against a dense route
+        Y = np.zeros(dims)
+        np.add.at(Y, (subs[:, 0], subs[:, 1], subs[:, 2]), 2 * w * (M - vals))
+        ref0 = np.einsum("ijk,jr,kr->ir", Y, A[1], A[2])
+        assert np.linalg.norm(grads[0] - ref0) < 1e-12 * np.linalg.norm(ref0)
+    for n in range(3):
+        for (k, j) in [(0, 0), (dims[n] - 1, 1)]:
+            h = 1e-6
+            Ap = [a.copy() for a in A]
+            Am = [a.copy() for a in A]
+            Ap[n][k, j] += h
+            Am[n][k, j] -= h
+            fd = (oracle.gcp(subs, vals, dims, Ap, loss, w, grads=False)
+                  - oracle.gcp(subs, vals, dims, Am, loss, w, grads=False)) / (2 * h)
+            assert abs(fd - grads[n][k, j]) < 1e-7 * max(1.0, abs(fd))
