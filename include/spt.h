@@ -75,7 +75,10 @@ typedef struct spt_tune {
     int32_t lanes_per_nnz;
     int32_t cols_per_lane;
     int32_t nnz_per_wave;
-    int32_t flags;  /* SPT_TUNE_DETERMINISTIC: see below */
+    int32_t flags;   /* SPT_TUNE_DETERMINISTIC: see below */
+    int32_t lds_kib; /* atomic algorithm: LDS budget of the per-workgroup combining table in KiB,
+                        at most 64; the table takes the largest power-of-two slot count that fits.
+                        0 = default: at most 128 slots within 64 KiB */
 } spt_tune;
 
 /* spt_tune.flags.  SPT_TUNE_DETERMINISTIC (permuted algorithms only): the rows a wave chunk

@@ -49,9 +49,9 @@ def _dev_check(t, name):
         raise ValueError(f"{name} must be a contiguous CUDA (HIP) tensor")
 
 
-def _tune(algo="auto", lanes=0, cols=0, chunk=0, deterministic=False):
+def _tune(algo="auto", lanes=0, cols=0, chunk=0, deterministic=False, lds_kib=0):
     return SptTune(_ALGOS[algo], int(lanes), int(cols), int(chunk),
-                   _lib.TUNE_DETERMINISTIC if deterministic else 0)
+                   _lib.TUNE_DETERMINISTIC if deterministic else 0, int(lds_kib))
 
 
 class SparseTensor:
@@ -172,7 +172,7 @@ def _factor_ptrs(factors, skip=-1):
 
 
 def mttkrp(X: SparseTensor, factors, mode: int, lam=None, algo="auto", lanes=0, cols=0,
-           chunk=0, vals=None, out=None, deterministic=False, stream=None):
+           chunk=0, vals=None, out=None, deterministic=False, lds_kib=0, stream=None):
     """Mode-`mode` MTTKRP (eq. (mttkrp)).  factors: d CUDA tensors (I_m, R) of one dtype
     (float64, float32 or bfloat16); lam: optional (R,) float64.  Returns V (I_n, R): float64
     for float64 factors, float32 otherwise."""
@@ -190,7 +190,7 @@ def mttkrp(X: SparseTensor, factors, mode: int, lam=None, algo="auto", lanes=0, 
             raise ValueError("lam must be float64")
     if vals is not None:
         _dev_check(vals, "vals")
-    tune = _tune(algo, lanes, cols, chunk, deterministic)
+    tune = _tune(algo, lanes, cols, chunk, deterministic, lds_kib)
     _lib.check(lib.spt_mttkrp(X.handle, int(mode), R, _factor_ptrs(factors, mode), fd,
                               ctypes.c_void_p(lam.data_ptr()) if lam is not None else None,
                               ctypes.c_void_p(vals.data_ptr()) if vals is not None else None,

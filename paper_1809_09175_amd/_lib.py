@@ -27,7 +27,7 @@ _c_d = ctypes.c_double
 class SptTune(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("lanes_per_nnz", ctypes.c_int32),
                 ("cols_per_lane", ctypes.c_int32), ("nnz_per_wave", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("lds_kib", ctypes.c_int32)]
 
 
 TUNE_DETERMINISTIC = 1

@@ -58,28 +58,32 @@ static int pow2_at_least(int x) {
     return p;
 }
 
-static int default_hbits(int R, int G, int CPL, int fdtype, int rq) {
-    // LDS budget for the hash table: 48 KiB minus the record staging buffer
+static int default_hbits(int R, int G, int CPL, int fdtype, int rq, int lds_kib) {
+    // hash table of 2^hbits slots in an LDS budget of lds_kib KiB minus the record staging
+    // buffer.  Without a budget the table is capped at 128 slots: on a 1e8-entry Zipf tensor
+    // (R = 16/32/64) that size beat larger tables, whose LDS cost resident workgroups per CU.
     const int at = (fdtype == SPT_F64) ? 8 : 4;
-    const int budget = 48 * 1024 - (kBlock / kWave) * kWave * rq * 16;
+    const int staging = (kBlock / kWave) * kWave * rq * 16;
+    const int budget = (lds_kib > 0 ? lds_kib : 64) * 1024 - staging;
+    const int cap = (lds_kib > 0) ? 12 : 7;
     const int per_slot = G * CPL * at + 4;
     int hb = 0;
-    while (hb < 12 && (2 << hb) * per_slot <= budget) ++hb;
+    while (hb < cap && (2 << hb) * per_slot <= budget) ++hb;
     (void)R;
     return hb;
 }
 
 // Default lane layout, from measurements on MI355X (1e8-entry Zipf tensor, R = 16/32/64): the
-// permuted kernel is fastest with few lanes per entry and wide per-lane loads (8 lanes x 2/4/8
-// FP32 columns), the atomic kernel with one column per lane (its LDS and global atomics are
-// per column either way).  Columns per lane must divide R.
+// permuted kernel is fastest with few lanes per entry and wide per-lane loads (4 lanes x 4 or
+// 8 FP32 columns up to R = 32, then 8 lanes x 8 columns), the atomic kernel with one column per
+// lane (its LDS and global atomics are per column either way).  Columns per lane must divide R.
 static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out) {
     int cpl = 1, G = 8;
+    (void)fdtype;
     if (algo == SPT_ALGO_PERMUTED) {
-        const int min_lanes = (fdtype == SPT_BF16) ? 4 : 8;
         const int opts[] = {8, 4, 2, 1};
         for (int c : opts) {
-            if (R % c != 0 || R / c < min_lanes) continue;
+            if (R % c != 0 || R / c < 4) continue;
             const int g = pow2_at_least(R / c);
             if (cfg_supported(g, c)) {
                 cpl = c;
@@ -89,10 +93,6 @@ static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out
                 return;
             }
         }
-    } else if (R <= 16 && R % 2 == 0 && R >= 8) {
-        *G_out = 8;
-        *cpl_out = 2;
-        return;
     }
     // one column per lane up to 64 columns, then wider lanes (R must then be even, and a
     // multiple of 4 above 128; other ranks are rejected by resolve_tune)
@@ -116,7 +116,7 @@ static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out
 
 int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tune *in,
                  spt_tune *out) {
-    spt_tune t = in ? *in : spt_tune{0, 0, 0, 0, 0};
+    spt_tune t = in ? *in : spt_tune{0, 0, 0, 0, 0, 0};
     if (t.algo == SPT_ALGO_AUTO)
         t.algo = X->srec[mode] != nullptr ? SPT_ALGO_PERMUTED_COPY
                                           : (X->permuted[mode] ? SPT_ALGO_PERMUTED : SPT_ALGO_ATOMIC);
@@ -147,6 +147,7 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
     }
     if (t.nnz_per_wave < 64 || t.nnz_per_wave % 64 != 0 || t.nnz_per_wave > (1 << 20))
         return SPT_EINVAL;
+    if (t.lds_kib < 0 || t.lds_kib > 64) return SPT_EINVAL;
     if (t.algo == SPT_ALGO_PRIVATIZED) {
         // the whole output must fit one workgroup's LDS next to the record staging buffer,
         // within 64 KiB so two workgroups share a CU
@@ -183,7 +184,8 @@ int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *facto
     a.slot_keys = nullptr;
     a.slot_vals = nullptr;
     a.In = (int)X->dims[mode];
-    a.hbits = default_hbits(R, t.lanes_per_nnz, t.cols_per_lane, fdtype, X->rec_words / 4);
+    a.hbits = default_hbits(R, t.lanes_per_nnz, t.cols_per_lane, fdtype, X->rec_words / 4,
+                            t.lds_kib);
     if (t.algo == SPT_ALGO_PRIVATIZED) {
         // privatised output: about two workgroups per CU, each adding a long contiguous range
         // into its LDS copy of V, so every row is flushed to HBM only once per workgroup

@@ -178,7 +178,9 @@ __device__ __forceinline__ void lds_record(const int4 *q, int *w) {
 // while the registers still allow 6-8 waves per SIMD
 template <int CPL, int G>
 struct UnrollFor {
-    static constexpr int raw = 32 / CPL;
+    // narrow groups (4 lanes) keep more entries in flight: measured best at 32 / CPL for them,
+    // 16 / CPL for groups of 8 lanes and more
+    static constexpr int raw = (G <= 4 ? 32 : 16) / CPL;
     static constexpr int value = raw < G ? raw : G;
 };
 
@@ -430,6 +432,23 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
                                            chunk, c0, slot_keys, slot_vals);
 }
 
+// Slot of output row k in a workgroup's LDS hash table of H = 2^hbits keys (-1 = free): found or
+// claimed within four linear probes from a multiplicative hash, else -1 (the caller then adds
+// to V directly).  Claims are never released during the workgroup's pass.
+__device__ __forceinline__ int table_slot(int *hkeys, int H, int hbits, int k) {
+    uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - hbits);
+    for (int probe = 0; probe < 4; ++probe) {
+        const int cur = __hip_atomic_load(&hkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == k) return (int)h;
+        if (cur == -1) {
+            const int old = atomicCAS(&hkeys[h], -1, k);
+            if (old == -1 || old == k) return (int)h;
+        }
+        h = (h + 1) & (uint32_t)(H - 1);
+    }
+    return -1;
+}
+
 // One workgroup processes storage positions [bc0, bc0 + 4 chunk) (one chunk per wavefront)
 // through the LDS table in smem4.  Every thread of the workgroup must call it.
 template <int D, int G, int CPL, class FT, class VT, class AT>
@@ -470,6 +489,28 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
     const int len = c1 > c0 ? (int)(c1 - c0) : 0;
     const int nb = (len + kWave - 1) / kWave;
+    if (!direct && H > 0) {
+        // heavy rows claim first: a row met at least twice among a wave's first 64 entries takes
+        // its slot before any other row can fill the table.  A row holding a large share of the
+        // entries then never falls back to direct adds of small terms into its large FP32 sum,
+        // which would round many of them away.
+        const int m = len < kWave ? len : kWave;
+        if (lane < m) {
+            s_rec[lane * RQ] = rec[(c0 + lane) * RQ];
+            if constexpr (RQ == 2) s_rec[lane * RQ + 1] = rec[(c0 + lane) * RQ + 1];
+        }
+        wave_sync();
+        const int k = lane < m ? lds_sub<RW>(&s_rec[lane * RQ], n) : -1;
+        int cnt = 0;
+        bool first = true;
+        for (int j = 0; j < m; ++j) {
+            const int kj = lds_sub<RW>(&s_rec[j * RQ], n);
+            cnt += (kj == k) ? 1 : 0;
+            if (kj == k && j < lane) first = false;
+        }
+        if (k >= 0 && cnt >= 2 && first) (void)table_slot(hkeys, H, hbits, k);
+        __syncthreads();
+    }
     for (int b = 0; b < nb; ++b) {
         const int off = b * kWave + lane;
         if (off < len) {
@@ -501,25 +542,7 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
                 const int k = kk[u];
                 if (k < 0) continue;
                 int slot = direct ? k : -1;
-                if (!direct && H > 0) {
-                    uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - hbits);
-                    for (int probe = 0; probe < 4; ++probe) {
-                        int cur = __hip_atomic_load(&hkeys[h], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (cur == k) {
-                            slot = (int)h;
-                            break;
-                        }
-                        if (cur == -1) {
-                            int old = atomicCAS(&hkeys[h], -1, k);
-                            if (old == -1 || old == k) {
-                                slot = (int)h;
-                                break;
-                            }
-                        }
-                        h = (h + 1) & (uint32_t)(H - 1);
-                    }
-                }
+                if (!direct && H > 0) slot = table_slot(hkeys, H, hbits, k);
                 if (colok) {
                     if (slot >= 0) {
 #pragma unroll

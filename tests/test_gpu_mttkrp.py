@@ -345,3 +345,52 @@ def test_privatized_short_mode(gpu):
         with pytest.raises(SptError) as e:
             spt.mttkrp(T, dev, 0, algo="privatized")
         assert e.value.code == -6
+
+
+def test_atomic_table_budget(gpu):
+    """Atomic kernel with explicit LDS budgets for its combining table (from a 2-slot table at
+    1 KiB to 64 KiB, FP32 and FP64): parity with the oracle; budgets beyond 64 KiB rejected."""
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import SptError
+    dims = (900, 70, 3000)
+    for kind, dtype in (("f32", np.float32), ("f64", np.float64)):
+        X = _small(kind, dims, 70_001, (1.3, 1.1, 0.0), seed=31)
+        T = _dev_tensor(X, dtype)
+        for R in (8, 32):
+            dev, ref = _factors(dims, R, seed=R + 1, kind=kind)
+            for kib in (0, 1, 8, 16, 48, 64):
+                for n in range(3):
+                    _log(f"table budget kind={kind} R={R} kib={kib} mode={n}")
+                    V = spt.mttkrp(T, dev, n, algo="atomic", lds_kib=kib)
+                    torch.cuda.synchronize()
+                    assert _relerr(V.cpu().numpy(),
+                                   oracle.mttkrp(X.subs, X.vals, dims, ref, n)) < TOL[kind]
+        with pytest.raises(SptError) as e:
+            spt.mttkrp(T, dev, 0, algo="atomic", lds_kib=65)
+        assert e.value.code == -1
+
+
+def test_atomic_heavy_row_accuracy(gpu):
+    """Rows holding a large share of the entries (Zipf exponent 1.1 over 200000 rows, the
+    hottest about a tenth of 8e6 entries) with a combining table far smaller than the distinct
+    rows one workgroup meets: the heavy rows' FP32 sums stay within the FP32 tolerance."""
+    import paper_1809_09175_amd as spt
+    dims = (200_000, 3000, 5000)
+    X = datagen.skewed_tensor(dims, 8_000_000, (1.1, 0.0, 0.0), seed=41)
+    T = _dev_tensor(X, np.float32)
+    R = 32
+    dev, ref = _factors(dims, R, seed=5, kind="f32")
+    counts = np.bincount(X.subs[:, 0], minlength=dims[0])
+    heavy = np.argsort(counts)[-6:]
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([heavy, rng.integers(0, dims[0], size=30)]))
+    s, v = _sampled_rows(X, 0, rows)
+    V_ref = oracle.mttkrp(s, v, dims, ref, 0)[rows]
+    hot = rows == heavy[-1]
+    for kib in (0, 8, 16):
+        _log(f"heavy rows kib={kib}")
+        V = spt.mttkrp(T, dev, 0, algo="atomic", lds_kib=kib)
+        torch.cuda.synchronize()
+        got = V[torch.from_numpy(rows).cuda()].cpu().numpy()
+        assert _relerr(got[hot], V_ref[hot]) < TOL["f32"], kib
+        assert _relerr(got, V_ref) < TOL["f32"], kib
