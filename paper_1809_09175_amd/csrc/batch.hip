@@ -137,21 +137,14 @@ static int batch_cfg_index(int algo, int d, int G, int CPL) {
 static size_t batch_smem_for(int cfg, int R, int *hbits) {
     const BatchCfg &c = kBatchCfgs[cfg];
     const int rq = 1;  // 3-way FP32 records are 16 bytes
+    (void)R;
     if (c.algo == SPT_ALGO_PERMUTED) {
         *hbits = 0;
-        const int NG = kWave / c.G;
-        return (size_t)(kBlock / kWave) *
-               (kWave * rq * 16 + 2 * NG * c.G * c.CPL * 4 + 2 * NG * 4 + 16);
+        return (size_t)(kBlock / kWave) * perm_shared_bytes(c.G, c.CPL, rq, 4);
     }
-    const int budget = 48 * 1024 - (kBlock / kWave) * kWave * rq * 16;
-    const int per_slot = c.G * c.CPL * 4 + 4;
-    int hb = 0;
-    while (hb < 12 && (2 << hb) * per_slot <= budget) ++hb;
+    const int hb = table_hbits(c.G, c.CPL, 4, rq, 0);
     *hbits = hb;
-    (void)R;
-    const int H = 1 << hb;
-    return (size_t)(kBlock / kWave) * kWave * rq * 16 + (size_t)(H > 2 ? H : 2) * 4 +
-           (size_t)H * c.G * c.CPL * 4;
+    return atomic_smem_bytes<float>(rq, 1 << hb, c.G * c.CPL);
 }
 
 extern "C" {

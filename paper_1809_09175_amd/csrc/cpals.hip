@@ -249,19 +249,50 @@ __device__ __forceinline__ double gcp_loss_term(int loss, double x, double m) {
     return (x - m) * (x - m);
 }
 
+// One entry of the model pass: x = its value, t = this lane's share of the model value,
+// sum_{j in lane} lambda_j prod_m A^(m)(l_m, j) (zero on lanes past column R, which still gather
+// the row's first columns so that the loads carry no lane-divergent branch).
+template <int D, int RW, int RQ, int CPL, class FT, class VT, class CT>
+__device__ __forceinline__ void model_entry(const int4 *q, const FactorSet<FT> &A, uint32_t rowbytes,
+                                            uint32_t colbytes, bool colok, const CT *lam, CT &t,
+                                            VT &x) {
+    int wv[RW];
+    lds_record<RQ>(q, wv);
+    x = rec_value<VT, RW>(wv);
+    CT f[D][CPL];
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        const uint32_t off = (uint32_t)wv[m] * rowbytes + colbytes;
+        load_cols<FT, CPL, CT>(reinterpret_cast<const FT *>(reinterpret_cast<const char *>(A.p[m]) + off),
+                               f[m]);
+    }
+    CT sum = 0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        CT p = lam[c];
+#pragma unroll
+        for (int m = 0; m < D; ++m) p *= f[m][c];
+        sum += p;
+    }
+    t = colok ? sum : (CT)0;
+}
+
 template <int D, int G, int CPL, class FT, class VT, class CT, int KIND>
 __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, int64_t P, int R,
                                                   FactorSet<FT> A, const double *__restrict__ lambda,
                                                   const CT *__restrict__ w, void *__restrict__ mout,
                                                   double *__restrict__ part, int chunk, int loss) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
-    constexpr int U = UnrollFor<CPL, G>::value;
+    constexpr int U = UnrollFor<KERNEL_MODEL, G, CPL, FT>::value;
     __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
     const bool colok = col0 < R;
-    const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
+    const uint32_t rowbytes = (uint32_t)R * sizeof(FT);
+    // lanes past column R read the row's first columns and contribute zero, so the gathers
+    // need no lane-divergent branch
+    const uint32_t colbytes = colok ? (uint32_t)col0 * sizeof(FT) : 0u;
     CT lam[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c)
@@ -284,33 +315,20 @@ __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, 
             for (int u0 = 0; u0 < cnt; u0 += U) {
                 CT t[U];
                 VT x[U];
+                if (u0 + U <= cnt) {  // whole unroll: straight-line code, all gathers in flight
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    t[u] = 0;
-                    x[u] = 0;
-                    if (u0 + u < cnt) {
-                        int wv[RW];
-                        lds_record<RQ>(&s_rec[wave][(g * G + u0 + u) * RQ], wv);
-                        x[u] = rec_value<VT, RW>(wv);
-                        if (colok) {
-                            // lambda_j prod_m A^(m)(l_m, j) for this lane's columns, then their sum
-                            CT p[CPL];
+                    for (int u = 0; u < U; ++u)
+                        model_entry<D, RW, RQ, CPL, FT, VT, CT>(&s_rec[wave][(g * G + u0 + u) * RQ], A,
+                                                                rowbytes, colbytes, colok, lam, t[u], x[u]);
+                } else {
 #pragma unroll
-                            for (int c = 0; c < CPL; ++c) p[c] = lam[c];
-#pragma unroll
-                            for (int m = 0; m < D; ++m) {
-                                CT f[CPL];
-                                const uint32_t off = (uint32_t)wv[m] * rowbytes + colbytes;
-                                load_cols<FT, CPL, CT>(reinterpret_cast<const FT *>(
-                                                           reinterpret_cast<const char *>(A.p[m]) + off), f);
-#pragma unroll
-                                for (int c = 0; c < CPL; ++c) p[c] *= f[c];
-                            }
-                            CT q = p[0];
-#pragma unroll
-                            for (int c = 1; c < CPL; ++c) q += p[c];
-                            t[u] = q;
-                        }
+                    for (int u = 0; u < U; ++u) {
+                        t[u] = 0;
+                        x[u] = 0;
+                        if (u0 + u < cnt)
+                            model_entry<D, RW, RQ, CPL, FT, VT, CT>(&s_rec[wave][(g * G + u0 + u) * RQ], A,
+                                                                    rowbytes, colbytes, colok, lam, t[u],
+                                                                    x[u]);
                     }
                 }
 #pragma unroll

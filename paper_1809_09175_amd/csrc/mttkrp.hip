@@ -58,38 +58,31 @@ static int pow2_at_least(int x) {
     return p;
 }
 
-static int default_hbits(int R, int G, int CPL, int fdtype, int rq, int lds_kib) {
-    // hash table of 2^hbits slots in an LDS budget of lds_kib KiB minus the record staging
-    // buffer.  Without a budget the table is capped at 128 slots: on a 1e8-entry Zipf tensor
-    // (R = 16/32/64) that size beat larger tables, whose LDS cost resident workgroups per CU.
-    const int at = (fdtype == SPT_F64) ? 8 : 4;
-    const int staging = (kBlock / kWave) * kWave * rq * 16;
-    const int budget = (lds_kib > 0 ? lds_kib : 64) * 1024 - staging;
-    const int cap = (lds_kib > 0) ? 12 : 7;
-    const int per_slot = G * CPL * at + 4;
-    int hb = 0;
-    while (hb < cap && (2 << hb) * per_slot <= budget) ++hb;
-    (void)R;
-    return hb;
-}
-
-// Default lane layout, from measurements on MI355X (1e8-entry Zipf tensor, R = 16/32/64): the
-// permuted kernel is fastest with few lanes per entry and wide per-lane loads (4 lanes x 4 or
-// 8 FP32 columns up to R = 32, then 8 lanes x 8 columns), the atomic kernel with one column per
-// lane (its LDS and global atomics are per column either way).  Columns per lane must divide R.
+// Default lane layout, from measurements on MI355X (1e8-entry Zipf tensor, R = 16/32/64, each
+// layout at its best unroll): the permuted kernel is fastest with 16 x 1, 8 x 4 and 16 x 4
+// (lanes x FP32 columns) at R = 16, 32, 64, and with 16 x 1, 16 x 2, 32 x 2 for BF16 factors;
+// i.e. one column per lane below 32 FP32 columns, then four (BF16: one up to 16, then two),
+// over as many lanes as cover R.  The atomic kernel is fastest with one column per lane (its LDS
+// and global atomics are per column either way).  Columns per lane must divide R.
 static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out) {
     int cpl = 1, G = 8;
-    (void)fdtype;
     if (algo == SPT_ALGO_PERMUTED) {
+        int c = (fdtype == SPT_BF16) ? (R <= 16 ? 1 : 2) : (R < 32 ? 1 : (R <= 64 ? 4 : 8));
+        while (c > 1 && R % c != 0) c >>= 1;
+        int g = pow2_at_least((R + c - 1) / c);
+        if (g < 8) g = 8;
+        if (cfg_supported(g, c)) {
+            *G_out = g;
+            *cpl_out = c;
+            return;
+        }
         const int opts[] = {8, 4, 2, 1};
-        for (int c : opts) {
-            if (R % c != 0 || R / c < 4) continue;
-            const int g = pow2_at_least(R / c);
-            if (cfg_supported(g, c)) {
-                cpl = c;
-                G = g;
-                *G_out = G;
-                *cpl_out = cpl;
+        for (int c2 : opts) {
+            if (R % c2 != 0 || R / c2 < 4) continue;
+            g = pow2_at_least(R / c2);
+            if (cfg_supported(g, c2)) {
+                *G_out = g;
+                *cpl_out = c2;
                 return;
             }
         }
@@ -184,8 +177,8 @@ int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *facto
     a.slot_keys = nullptr;
     a.slot_vals = nullptr;
     a.In = (int)X->dims[mode];
-    a.hbits = default_hbits(R, t.lanes_per_nnz, t.cols_per_lane, fdtype, X->rec_words / 4,
-                            t.lds_kib);
+    a.hbits = table_hbits(t.lanes_per_nnz, t.cols_per_lane, fdtype == SPT_F64 ? 8 : 4,
+                          X->rec_words / 4, t.lds_kib);
     if (t.algo == SPT_ALGO_PRIVATIZED) {
         // privatised output: about two workgroups per CU, each adding a long contiguous range
         // into its LDS copy of V, so every row is flushed to HBM only once per workgroup

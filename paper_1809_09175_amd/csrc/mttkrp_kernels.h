@@ -137,30 +137,53 @@ __device__ __forceinline__ void atomic_cols(AT *__restrict__ p, const AT *v) {
     for (int c = 0; c < CPL; ++c) atomic_add_f(p + c, v[c]);
 }
 
+// The factor matrices of the modes other than n, in increasing mode order (other mode j is
+// mode j below n, mode j + 1 from n on), chosen once per wavefront: the per-entry gathers then
+// carry no branch on the run-time mode, so the loads of several entries can be in flight at
+// once instead of each waiting behind a branch.
+template <int D>
+struct OtherModes {
+    const char *base[D - 1];
+    int up[D - 1];  // all ones when other mode j is mode j + 1, else zero
+};
+
+template <int D, class FT>
+__device__ __forceinline__ OtherModes<D> other_modes(const FactorSet<FT> &A, int n) {
+    OtherModes<D> o;
+#pragma unroll
+    for (int j = 0; j < D - 1; ++j) {
+        const bool up = j >= n;
+        o.base[j] = reinterpret_cast<const char *>(up ? A.p[j + 1] : A.p[j]);
+        o.up[j] = up ? -1 : 0;
+    }
+    return o;
+}
+
 // Product row of one entry: t[c] = x * lambda_j * prod_{m != n} A^(m)(l_m, j), for this lane's
 // columns j = col0 .. col0+CPL-1 (multiply order as in Sec. 4.1: x times the weight first,
 // then each other mode in increasing order).  Factor rows are addressed with 32-bit byte
 // offsets from the (wave-uniform) matrix base, so each gather needs one offset register and
 // the hardware's scalar-base addressing; every factor matrix must be smaller than 4 GiB.
+// Lanes past column R pass colbytes = 0: they read the row's first columns and their products
+// are never stored, which keeps the gathers free of lane-divergent branches.
 template <int D, int RW, int CPL, class FT, class VT, class AT>
-__device__ __forceinline__ void entry_product(const int *w, int n, uint32_t rowbytes,
-                                              uint32_t colbytes, bool colok,
-                                              const FactorSet<FT> &A, const AT *lam, AT *t) {
+__device__ __forceinline__ void entry_product(const int *w, const OtherModes<D> &om,
+                                              uint32_t rowbytes, uint32_t colbytes,
+                                              const AT *lam, AT *t) {
+    AT f[D - 1][CPL];
+#pragma unroll
+    for (int j = 0; j < D - 1; ++j) {
+        const int sub = (w[j] & ~om.up[j]) | (w[j + 1] & om.up[j]);
+        const uint32_t off = (uint32_t)sub * rowbytes + colbytes;
+        load_cols<FT, CPL, AT>(reinterpret_cast<const FT *>(om.base[j] + off), f[j]);
+    }
     const AT x = (AT)rec_value<VT, RW>(w);
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) t[c] = x * lam[c];
-    if (colok) {
+    for (int c = 0; c < CPL; ++c) {
+        AT v = x * lam[c];
 #pragma unroll
-        for (int m = 0; m < D; ++m) {
-            if (m != n) {
-                AT f[CPL];
-                const uint32_t off = (uint32_t)w[m] * rowbytes + colbytes;
-                load_cols<FT, CPL, AT>(
-                    reinterpret_cast<const FT *>(reinterpret_cast<const char *>(A.p[m]) + off), f);
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) t[c] *= f[c];
-            }
-        }
+        for (int j = 0; j < D - 1; ++j) v *= f[j][c];
+        t[c] = v;
     }
 }
 
@@ -176,13 +199,58 @@ __device__ __forceinline__ void lds_record(const int4 *q, int *w) {
 
 // entries gathered ahead per lane group: enough loads in flight to cover the gather latency
 // while the registers still allow 6-8 waves per SIMD
-template <int CPL, int G>
+// Entries a lane group gathers ahead (its loads in flight at once), per kernel, lane layout and
+// factor element size.  Measured on MI355X (1e8-entry Zipf tensor, R = 16/32/64, U in
+// {1, 2, 4, 8, 16}); with U = 1 the compiler still overlaps consecutive entries, which is why
+// some wide layouts do best there.  Unmeasured layouts: 32 / CPL entries for 4-lane groups,
+// 16 / CPL for wider ones.  Never more than G (the entries a group stages per batch).
+enum { KERNEL_PERM = 0, KERNEL_ATOMIC = 1, KERNEL_MODEL = 2 };
+
+__host__ __device__ constexpr int unroll_for(int kernel, int G, int CPL, int fbytes) {
+    int u = (G <= 4 ? 32 : 16) / CPL;
+    if (kernel == KERNEL_PERM && fbytes == 4) {
+        if (G == 8 && CPL == 8) u = 1;
+        if (G == 16 && CPL == 4) u = 1;
+        if (G == 8 && CPL == 4) u = 8;
+        if (G == 16 && CPL == 2) u = 8;
+        if (G == 32 && CPL == 2) u = 8;
+    } else if (kernel == KERNEL_PERM && fbytes == 2) {
+        if (G >= 8 && (CPL == 8 || (CPL == 4 && G <= 16))) u = 1;
+        if (G == 16 && CPL == 2) u = 8;
+        if (G == 32 && CPL == 2) u = 8;
+    } else if (kernel == KERNEL_ATOMIC && CPL == 1) {
+        u = (G <= 32) ? 1 : 4;
+    }
+    if (u < 1) u = 1;
+    return u < G ? u : G;
+}
+
+template <int KERNEL, int G, int CPL, class FT>
 struct UnrollFor {
-    // narrow groups (4 lanes) keep more entries in flight: measured best at 32 / CPL for them,
-    // 16 / CPL for groups of 8 lanes and more
-    static constexpr int raw = (G <= 4 ? 32 : 16) / CPL;
-    static constexpr int value = raw < G ? raw : G;
+    static constexpr int value = unroll_for(KERNEL, G, CPL, (int)sizeof(FT));
 };
+
+// Bytes of one wavefront's PermShared (the batched kernel sizes its dynamic LDS with it).
+inline size_t perm_shared_bytes(int G, int CPL, int RQ, int at_bytes) {
+    const int NG = kWave / G;
+    const size_t b = (size_t)kWave * RQ * 16 + (size_t)2 * NG * G * CPL * at_bytes +
+                     (size_t)2 * NG * 4;
+    return (b + 15) / 16 * 16;
+}
+
+// log2 of the slot count of the atomic kernel's LDS combining table: the largest power of two
+// whose slots (G * CPL accumulators and a key each) fit an LDS budget of lds_kib KiB minus the
+// record staging buffer; without a budget, at most 128 slots within 64 KiB (on a 1e8-entry Zipf
+// tensor at R = 16/32/64, larger tables lost more in resident workgroups per CU than they won).
+inline int table_hbits(int G, int CPL, int at_bytes, int RQ, int lds_kib) {
+    const int staging = (kBlock / kWave) * kWave * RQ * 16;
+    const int budget = (lds_kib > 0 ? lds_kib : 64) * 1024 - staging;
+    const int cap = (lds_kib > 0) ? 12 : 7;
+    const int per_slot = G * CPL * at_bytes + 4;
+    int hb = 0;
+    while (hb < cap && (2 << hb) * per_slot <= budget) ++hb;
+    return hb;
+}
 
 // LDS of one wavefront in the permuted kernel: the staged records of the current batch and the
 // boundary partial rows (first and last row of every lane group's slice).
@@ -208,12 +276,14 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                                                 AT *__restrict__ slot_vals = nullptr) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int NG = kWave / G;
-    constexpr int U = UnrollFor<CPL, G>::value;
+    constexpr int U = UnrollFor<KERNEL_PERM, G, CPL, FT>::value;
     const int lane = threadIdx.x & 63;
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
     const bool colok = col0 < R;
-    const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
+    const uint32_t rowbytes = (uint32_t)R * sizeof(FT);
+    const uint32_t colbytes = colok ? (uint32_t)col0 * sizeof(FT) : 0u;
+    const OtherModes<D> om = other_modes<D>(A, n);
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
     const int S = chunk / NG;  // slice per group
     const int64_t gb = c0 + (int64_t)g * S;
@@ -293,7 +363,7 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                     int w[RW];
                     lds_record<RQ>(sr + (s0 + u) * RQ, w);
                     kk[u] = lds_sub<RW>(sr + (s0 + u) * RQ, n);
-                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, rowbytes, colbytes, colok, A, lam, t[u]);
+                    entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
                 }
             } else {
 #pragma unroll
@@ -303,7 +373,7 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                         int w[RW];
                         lds_record<RQ>(sr + (s0 + u) * RQ, w);
                         kk[u] = lds_sub<RW>(sr + (s0 + u) * RQ, n);
-                        entry_product<D, RW, CPL, FT, VT, AT>(w, n, rowbytes, colbytes, colok, A, lam, t[u]);
+                        entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
                     }
                 }
             }
@@ -461,7 +531,7 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
                                                   int64_t bc0) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int RP = G * CPL;
-    constexpr int U = UnrollFor<CPL, G>::value;
+    constexpr int U = UnrollFor<KERNEL_ATOMIC, G, CPL, FT>::value;
     int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
     // hbits > 0: hash table of 2^hbits rows; hbits == 0: no table; hbits < 0: "privatised"
     // output, one LDS row per output row k < In (slot = k, no keys)
@@ -474,7 +544,9 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
     const bool colok = col0 < R;
-    const uint32_t rowbytes = (uint32_t)R * sizeof(FT), colbytes = (uint32_t)col0 * sizeof(FT);
+    const uint32_t rowbytes = (uint32_t)R * sizeof(FT);
+    const uint32_t colbytes = colok ? (uint32_t)col0 * sizeof(FT) : 0u;
+    const OtherModes<D> om = other_modes<D>(A, n);
     if (!direct)
         for (int i = tid; i < H; i += kBlock) hkeys[i] = -1;
     for (int i = tid; i < H * RP; i += kBlock) hvals[i] = 0;
@@ -526,15 +598,25 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
         for (int s0 = 0; s0 < cnt; s0 += U) {
             AT t[U][CPL];
             int kk[U];
+            if (s0 + U <= cnt) {  // whole unroll: straight-line code, all gathers in flight
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int s = s0 + u;
-                kk[u] = -1;
-                if (s < cnt) {
+                for (int u = 0; u < U; ++u) {
                     int w[RW];
-                    lds_record<RQ>(&s_rec[(g * G + s) * RQ], w);
-                    kk[u] = lds_sub<RW>(&s_rec[(g * G + s) * RQ], n);
-                    entry_product<D, RW, CPL, FT, VT, AT>(w, n, rowbytes, colbytes, colok, A, lam, t[u]);
+                    lds_record<RQ>(&s_rec[(g * G + s0 + u) * RQ], w);
+                    kk[u] = lds_sub<RW>(&s_rec[(g * G + s0 + u) * RQ], n);
+                    entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int s = s0 + u;
+                    kk[u] = -1;
+                    if (s < cnt) {
+                        int w[RW];
+                        lds_record<RQ>(&s_rec[(g * G + s) * RQ], w);
+                        kk[u] = lds_sub<RW>(&s_rec[(g * G + s) * RQ], n);
+                        entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
+                    }
                 }
             }
 #pragma unroll
