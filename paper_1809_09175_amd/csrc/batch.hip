@@ -34,7 +34,9 @@ struct BatchItem {
     X(5, SPT_ALGO_ATOMIC, 3, 8, 2)           \
     X(6, SPT_ALGO_ATOMIC, 3, 8, 4)           \
     X(7, SPT_ALGO_ATOMIC, 3, 16, 2)          \
-    X(8, SPT_ALGO_ATOMIC, 3, 16, 4)
+    X(8, SPT_ALGO_ATOMIC, 3, 16, 4)          \
+    X(9, SPT_ALGO_PERMUTED, 3, 8, 1)         \
+    X(10, SPT_ALGO_PERMUTED, 3, 16, 1)
 
 struct BatchCfg {
     int algo, d, G, CPL;
@@ -45,6 +47,12 @@ static const BatchCfg kBatchCfgs[] = {
 #undef SPT_CFG_ROW
 };
 constexpr int kNumBatchCfgs = sizeof(kBatchCfgs) / sizeof(kBatchCfgs[0]);
+
+// The batched kernel holds every configuration's code, so its register allocation is the
+// largest of them.  It runs with an unroll of 2 under a 4-waves-per-SIMD register cap (128
+// VGPRs): on the 64-tensor batch that beat unrolls 1 and 4, capped or not (1.13 ms against
+// 1.25-1.50 ms), the few spills it costs included.
+constexpr int kBatchUnroll = 2;
 
 template <int ALGO, int D, int G, int CPL, class FT>
 __device__ __forceinline__ void batch_unit(int4 *smem4, const BatchItem &it, int64_t u) {
@@ -59,16 +67,16 @@ __device__ __forceinline__ void batch_unit(int4 *smem4, const BatchItem &it, int
         const int wave = threadIdx.x >> 6;
         const int64_t c0 = bc0 + (int64_t)wave * it.chunk;
         if (c0 < it.P)
-            perm_wave_chunk<D, G, CPL, FT, float, float>(sm[wave], it.rec, it.perm, it.srec, it.P, it.n,
+            perm_wave_chunk<D, G, CPL, FT, float, float, kBatchUnroll>(sm[wave], it.rec, it.perm, it.srec, it.P, it.n,
                                                          it.R, A, nullptr, nullptr, V, it.chunk, c0);
     } else {
-        atomic_block_unit<D, G, CPL, FT, float, float>(smem4, it.rec, it.P, it.n, it.R, A, nullptr,
+        atomic_block_unit<D, G, CPL, FT, float, float, kBatchUnroll>(smem4, it.rec, it.P, it.n, it.R, A, nullptr,
                                                        nullptr, V, it.chunk, it.hbits, 0, bc0);
     }
 }
 
 template <class FT>
-__global__ __launch_bounds__(kBlock) void k_mttkrp_batched(const BatchItem *__restrict__ items,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_mttkrp_batched(const BatchItem *__restrict__ items,
                                                            int nitems, int64_t total_units,
                                                            unsigned long long *counter) {
     extern __shared__ int4 smem4[];

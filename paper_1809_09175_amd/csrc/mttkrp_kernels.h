@@ -220,6 +220,8 @@ __host__ __device__ constexpr int unroll_for(int kernel, int G, int CPL, int fby
         if (G == 32 && CPL == 2) u = 8;
     } else if (kernel == KERNEL_ATOMIC && CPL == 1) {
         u = (G <= 32) ? 1 : 4;
+    } else if (kernel == KERNEL_MODEL) {
+        u = 1;  // fit 2.8 vs 3.6 ms at R = 32 (unroll 4); model values alike
     }
     if (u < 1) u = 1;
     return u < G ? u : G;
@@ -263,7 +265,7 @@ struct PermShared {
 };
 
 // One wavefront processes sorted positions [c0, min(c0 + chunk, P)) of mode n (c0 < P).
-template <int D, int G, int CPL, class FT, class VT, class AT>
+template <int D, int G, int CPL, class FT, class VT, class AT, int UMAX = 64>
 __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &sm,
                                                 const int4 *__restrict__ rec,
                                                 const int32_t *__restrict__ perm,
@@ -276,7 +278,8 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                                                 AT *__restrict__ slot_vals = nullptr) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int NG = kWave / G;
-    constexpr int U = UnrollFor<KERNEL_PERM, G, CPL, FT>::value;
+    constexpr int U0 = UnrollFor<KERNEL_PERM, G, CPL, FT>::value;
+    constexpr int U = U0 < UMAX ? U0 : UMAX;
     const int lane = threadIdx.x & 63;
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
@@ -521,7 +524,7 @@ __device__ __forceinline__ int table_slot(int *hkeys, int H, int hbits, int k) {
 
 // One workgroup processes storage positions [bc0, bc0 + 4 chunk) (one chunk per wavefront)
 // through the LDS table in smem4.  Every thread of the workgroup must call it.
-template <int D, int G, int CPL, class FT, class VT, class AT>
+template <int D, int G, int CPL, class FT, class VT, class AT, int UMAX = 64>
 __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__restrict__ rec,
                                                   int64_t P, int n, int R, const FactorSet<FT> &A,
                                                   const double *__restrict__ lambda,
@@ -531,7 +534,8 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
                                                   int64_t bc0) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int RP = G * CPL;
-    constexpr int U = UnrollFor<KERNEL_ATOMIC, G, CPL, FT>::value;
+    constexpr int U0 = UnrollFor<KERNEL_ATOMIC, G, CPL, FT>::value;
+    constexpr int U = U0 < UMAX ? U0 : UMAX;
     int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
     // hbits > 0: hash table of 2^hbits rows; hbits == 0: no table; hbits < 0: "privatised"
     // output, one LDS row per output row k < In (slot = k, no keys)

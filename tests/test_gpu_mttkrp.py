@@ -239,14 +239,16 @@ def _sampled_rows(X, n, rows):
 
 @pytest.mark.slow
 def test_powerlaw3_full_size_sampled(gpu):
-    """The 1e8-entry power-law tensor at R=32, in the benchmark's launch configuration:
-    selected rows of V (the hottest row of each mode, a ragged tail of random rows) against
-    the oracle on exactly the entries that feed them."""
+    """The 1e8-entry power-law tensor at R=32, in the benchmark's launch configuration (default
+    layouts; "auto" is the timed path, the traversal over mode-sorted record copies): selected
+    rows of V (the hottest row of each mode, a ragged tail of random rows) against the oracle on
+    exactly the entries that feed them."""
     import paper_1809_09175_amd as spt
     _log("powerlaw3 full size: generating")
     X = datagen.powerlaw3()
     T = _dev_tensor(X, np.float32)
     T.permute()
+    T.sort_copy()
     R = 32
     dev, ref = _factors(X.dims, R, seed=7, kind="f32")
     rng = np.random.default_rng(0)
@@ -256,7 +258,7 @@ def test_powerlaw3_full_size_sampled(gpu):
         rows = np.unique(np.concatenate([[hot], rng.integers(0, X.dims[n], size=40)]))
         s, v = _sampled_rows(X, n, rows)
         V_ref = oracle.mttkrp(s, v, X.dims, ref, n)[rows]
-        for algo in ("atomic", "permuted"):
+        for algo in ("atomic", "permuted", "permuted_copy", "auto"):
             _log(f"powerlaw3 n={n} {algo}")
             V = spt.mttkrp(T, dev, n, algo=algo)
             torch.cuda.synchronize()
