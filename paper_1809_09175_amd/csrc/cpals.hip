@@ -66,8 +66,10 @@ __device__ double block_sum_f64(double v) {
 
 // Tile of rows -> per-block partial Gram.  With NORMALIZE, the tile comes from the FP64 solve
 // output Y: a = y / lambda (columns with lambda > 0), stored to A in FT, and the Gram uses the
-// stored (rounded) values.
-template <class FT, bool NORMALIZE>
+// stored (rounded) values.  Thread (ta, tb) of a 16 x 16 arrangement accumulates the B x B block
+// of G at rows ta*B.., columns tb*B.. (B = ceil(R / 16)): 2B LDS reads feed B*B FMAs, and every
+// entry still sums its rows in increasing order.
+template <class FT, bool NORMALIZE, int B>
 __global__ __launch_bounds__(kBlock) void k_gram_partial(const FT *__restrict__ Ain,
                                                          const double *__restrict__ Y,
                                                          const double *__restrict__ lambda,
@@ -75,10 +77,12 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const FT *__restrict__ 
                                                          double *__restrict__ gpart) {
     __shared__ double tile[kGramRows][kCpMaxR + 1];
     const int tid = threadIdx.x;
-    const int RR = R * R;
-    double acc[kCpMaxR * kCpMaxR / kBlock];  // up to 16 entries of G per thread
+    const int a0 = (tid >> 4) * B, b0 = (tid & 15) * B;
+    double acc[B][B];
 #pragma unroll
-    for (int e = 0; e < kCpMaxR * kCpMaxR / kBlock; ++e) acc[e] = 0.0;
+    for (int x = 0; x < B; ++x)
+#pragma unroll
+        for (int y = 0; y < B; ++y) acc[x][y] = 0.0;
     for (int64_t r0 = (int64_t)blockIdx.x * kGramRows; r0 < I; r0 += (int64_t)gridDim.x * kGramRows) {
         const int nrows = (I - r0 < kGramRows) ? (int)(I - r0) : kGramRows;
         for (int e = tid; e < kGramRows * R; e += kBlock) {
@@ -99,46 +103,50 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const FT *__restrict__ 
             tile[rr][c] = v;
         }
         __syncthreads();
+        if (a0 < R && b0 < R) {
+            for (int rr = 0; rr < nrows; ++rr) {
+                double va[B], vb[B];
 #pragma unroll
-        for (int e = 0; e < kCpMaxR * kCpMaxR / kBlock; ++e) {
-            const int ab = tid + e * kBlock;
-            if (ab < RR) {
-                const int a = ab / R, b = ab - a * R;
-                double s = acc[e];
-                for (int rr = 0; rr < nrows; ++rr) s += tile[rr][a] * tile[rr][b];
-                acc[e] = s;
+                for (int x = 0; x < B; ++x) {
+                    va[x] = tile[rr][a0 + x];  // blocks past column R are never stored
+                    vb[x] = tile[rr][b0 + x];
+                }
+#pragma unroll
+                for (int x = 0; x < B; ++x)
+#pragma unroll
+                    for (int y = 0; y < B; ++y) acc[x][y] += va[x] * vb[y];
             }
         }
         __syncthreads();
     }
+    const int RR = R * R;
 #pragma unroll
-    for (int e = 0; e < kCpMaxR * kCpMaxR / kBlock; ++e) {
-        const int ab = tid + e * kBlock;
-        if (ab < RR) gpart[(int64_t)blockIdx.x * RR + ab] = acc[e];
-    }
+    for (int x = 0; x < B; ++x)
+#pragma unroll
+        for (int y = 0; y < B; ++y)
+            if (a0 + x < R && b0 + y < R)
+                gpart[(int64_t)blockIdx.x * RR + (a0 + x) * R + (b0 + y)] = acc[x][y];
 }
 
-// out[i] = sum over the partials b = 0..nblk-1 in order (deterministic); one thread per entry,
-// the loads of consecutive partials issued ahead of the additions
+// out[i] = sum over the partials b = 0..nblk-1, one wavefront per entry: lane l adds partials
+// l, l + 64, ... in order, then the 64 lane sums combine in a fixed butterfly.  The order is
+// fixed for a given nblk, so the result is reproducible run to run.
 __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__ part, int nblk,
                                                       int len, double *__restrict__ out) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= len) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    if (i >= len) return;  // whole wavefront
     double s = 0.0;
-    int b = 0;
-    for (; b + 8 <= nblk; b += 8) {
-        double v[8];
+    for (int b = lane; b < nblk; b += kWave) s += part[(int64_t)b * len + i];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = part[(int64_t)(b + k) * len + i];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) s += v[k];
-    }
-    for (; b < nblk; ++b) s += part[(int64_t)b * len + i];
-    out[i] = s;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) out[i] = s;
 }
 
 // ------------------------------------------------------------------------------------------
-// Hadamard product of the other modes' Grams and its Cholesky factor (one workgroup).  Same
+// Hadamard product of the other modes' Grams (the whole workgroup) and its Cholesky factor (the
+// first wavefront alone: lane r owns row r, so the column steps synchronise with wave barriers
+// instead of workgroup barriers).  Same
 // column-by-column order as the textbook algorithm; no FMA contraction here so the factor
 // follows the plain definition's rounding.
 // ------------------------------------------------------------------------------------------
@@ -160,6 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restri
         Lc[ab / R][ab % R] = 0.0;
     }
     __syncthreads();
+    if (tid >= kWave) return;
     double maxdiag = 0.0;
     for (int k = 0; k < R; ++k) maxdiag = S[k][k] > maxdiag ? S[k][k] : maxdiag;
     const double tol = (double)R * 2.220446049250313e-16 * maxdiag;
@@ -174,65 +183,185 @@ __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restri
             lcc_s = sqrt(piv);
             Lc[c][c] = lcc_s;
         }
-        __syncthreads();
+        wave_sync();
         const double lcc = lcc_s;
-        for (int r = c + 1 + tid; r < R; r += kBlock) {
+        for (int r = c + 1 + tid; r < R; r += kWave) {
             double s = S[r][c];
             for (int k = 0; k < c; ++k) s -= Lc[r][k] * Lc[c][k];
             Lc[r][c] = s / lcc;
         }
-        __syncthreads();
+        wave_sync();
     }
-    for (int ab = tid; ab < R * R; ab += kBlock) L[ab] = Lc[ab / R][ab % R];
+    for (int ab = tid; ab < R * R; ab += kWave) L[ab] = Lc[ab / R][ab % R];
     if (tid == 0 && bad) raise_status(st, SPT_ESINGULAR);
 }
 
 // ------------------------------------------------------------------------------------------
 // Row solves: row k of the unnormalised factor solves  a Gamma = v  with Gamma = L L^T
-// (forward substitution with L, then back substitution with L^T), one thread per row, in the
-// textbook order.  The column 2-norms come afterwards from the diagonal of Y^T Y.
-// ------------------------------------------------------------------------------------------
-template <int RMAX, class VT>
+// (forward substitution with L, then back substitution with L^T), in the textbook order.  One
+// thread solves NR rows at once (NR = 2 up to R = 32) so that every L entry read from LDS feeds
+// NR rows; L and its transpose sit in LDS zero-padded to RMAX columns and are read two entries
+// per load (padded terms subtract 0 * 0 and leave the sums unchanged).  With VEC (R a multiple of
+// 4) rows of V and Y move with 16-byte accesses.  The column 2-norms come afterwards from the
+// column sums of squares of Y.
+template <int RMAX, int NR, bool VEC, class VT>
 __global__ __launch_bounds__(kBlock) void k_solve_rows(const VT *__restrict__ V, int64_t I, int R,
                                                        const double *__restrict__ Lg,
                                                        double *__restrict__ Y) {
 #pragma clang fp contract(off)
-    __shared__ double L[RMAX * RMAX];
+    __shared__ double2 L2[RMAX][RMAX / 2];   // L[c][q] at L2[c][q/2], lower triangle
+    __shared__ double2 LT2[RMAX][RMAX / 2];  // L[q][c] at LT2[c][q/2]
+    __shared__ double dg[RMAX];
     const int tid = threadIdx.x;
-    for (int e = tid; e < R * R; e += kBlock) L[e] = Lg[e];
+    double *Lf = reinterpret_cast<double *>(&L2[0][0]);
+    double *LTf = reinterpret_cast<double *>(&LT2[0][0]);
+    for (int e = tid; e < RMAX * RMAX; e += kBlock) {
+        const int r = e / RMAX, c = e - r * RMAX;
+        const double v = (r < R && c < R) ? Lg[r * R + c] : 0.0;
+        Lf[r * RMAX + c] = v;
+        LTf[c * RMAX + r] = v;
+        if (r == c) dg[r] = v;
+    }
     __syncthreads();
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + tid; k < I; k += (int64_t)gridDim.x * kBlock) {
-        double a[RMAX];
+    // one pass per thread (the grid covers every row), so no L value is worth keeping in
+    // registers across iterations
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t k0 = (int64_t)blockIdx.x * kBlock + tid;
+    {
+        double a[NR][RMAX];
 #pragma unroll
-        for (int c = 0; c < RMAX; ++c) a[c] = (c < R) ? (double)V[k * R + c] : 0.0;
+        for (int h = 0; h < NR; ++h) {
+            const int64_t k = k0 + h * stride;
+            if constexpr (VEC) {
+                // 16-byte loads: a row is read with R/4 (FP32) or R/2 (FP64) instructions
+                constexpr int W = 16 / (int)sizeof(VT);
+#pragma unroll
+                for (int c = 0; c < RMAX; c += W) {
+                    if (c < R && k < I) {
+                        if constexpr (W == 4) {
+                            const float4 v = *reinterpret_cast<const float4 *>(V + k * R + c);
+                            a[h][c] = v.x; a[h][c + 1] = v.y; a[h][c + 2] = v.z; a[h][c + 3] = v.w;
+                        } else {
+                            const double2 v = *reinterpret_cast<const double2 *>(V + k * R + c);
+                            a[h][c] = v.x; a[h][c + 1] = v.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) a[h][c + w] = 0.0;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < RMAX; ++c) a[h][c] = (c < R && k < I) ? (double)V[k * R + c] : 0.0;
+            }
+        }
+        // forward: a_c = (v_c - sum_{q<c} L[c][q] a_q) / L[c][c]
 #pragma unroll
         for (int c = 0; c < RMAX; ++c) {
             if (c < R) {
-                double s = a[c];
+                double sv[NR];
 #pragma unroll
-                for (int q = 0; q < c; ++q) s -= L[c * R + q] * a[q];
-                a[c] = s / L[c * R + c];
+                for (int h = 0; h < NR; ++h) sv[h] = a[h][c];
+#pragma unroll
+                for (int q = 0; q + 1 < c; q += 2) {
+                    const double2 l = L2[c][q / 2];
+#pragma unroll
+                    for (int h = 0; h < NR; ++h) {
+                        sv[h] -= l.x * a[h][q];
+                        sv[h] -= l.y * a[h][q + 1];
+                    }
+                }
+                if (c & 1) {
+                    const double l = Lf[c * RMAX + c - 1];
+#pragma unroll
+                    for (int h = 0; h < NR; ++h) sv[h] -= l * a[h][c - 1];
+                }
+                const double d = dg[c];
+#pragma unroll
+                for (int h = 0; h < NR; ++h) a[h][c] = sv[h] / d;
             }
         }
+        // backward: a_c = (a_c - sum_{q>c} L[q][c] a_q) / L[c][c], q ascending
 #pragma unroll
         for (int c = RMAX - 1; c >= 0; --c) {
             if (c < R) {
-                double s = a[c];
+                double sv[NR];
 #pragma unroll
-                for (int q = c + 1; q < RMAX; ++q)
-                    if (q < R) s -= L[q * R + c] * a[q];
-                a[c] = s / L[c * R + c];
+                for (int h = 0; h < NR; ++h) sv[h] = a[h][c];
+                int q = c + 1;
+                if (q & 1) {
+                    if (q < RMAX) {
+                        const double l = LTf[c * RMAX + q];
+#pragma unroll
+                        for (int h = 0; h < NR; ++h) sv[h] -= l * a[h][q];
+                    }
+                    ++q;
+                }
+#pragma unroll
+                for (; q + 1 < RMAX + 1 && q < RMAX; q += 2) {
+                    const double2 l = LT2[c][q / 2];
+#pragma unroll
+                    for (int h = 0; h < NR; ++h) {
+                        sv[h] -= l.x * a[h][q];
+                        sv[h] -= l.y * a[h][q + 1];
+                    }
+                }
+                const double d = dg[c];
+#pragma unroll
+                for (int h = 0; h < NR; ++h) a[h][c] = sv[h] / d;
             }
         }
 #pragma unroll
-        for (int c = 0; c < RMAX; ++c)
-            if (c < R) Y[k * R + c] = a[c];
+        for (int h = 0; h < NR; ++h) {
+            const int64_t k = k0 + h * stride;
+            if (k < I) {
+                if constexpr (VEC) {
+#pragma unroll
+                    for (int c = 0; c < RMAX; c += 2)
+                        if (c < R) *reinterpret_cast<double2 *>(Y + k * R + c) = make_double2(a[h][c], a[h][c + 1]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < RMAX; ++c)
+                        if (c < R) Y[k * R + c] = a[h][c];
+                }
+            }
+        }
     }
 }
 
-// lambda_j = sqrt((Y^T Y)_jj)
-__global__ void k_norms_from_gram(const double *__restrict__ GY, int R, double *__restrict__ lambda) {
-    for (int c = threadIdx.x; c < R; c += blockDim.x) lambda[c] = sqrt(GY[c * R + c]);
+// Column sums of squares of Y (I x R, FP64) as per-block partials in a fixed order: thread
+// (q, c) = (tid / R, tid % R) sums column c over rows q, q + Q, ... of the block's 64-row tiles
+// (Q = 256 / R rows per pass, consecutive threads read consecutive addresses), then the block
+// adds its Q partial sums per column in order q = 0..Q-1.
+__global__ __launch_bounds__(kBlock) void k_colsq_partial(const double *__restrict__ Y, int64_t I,
+                                                          int R, double *__restrict__ part) {
+    __shared__ double red[kBlock];
+    const int tid = threadIdx.x;
+    const int Q = kBlock / R;
+    const int q = tid / R, c = tid - q * R;
+    double acc = 0.0;
+    if (q < Q) {
+        for (int64_t r0 = (int64_t)blockIdx.x * kGramRows; r0 < I;
+             r0 += (int64_t)gridDim.x * kGramRows) {
+            const int64_t r1 = (r0 + kGramRows < I) ? r0 + kGramRows : I;
+            for (int64_t r = r0 + q; r < r1; r += Q) {
+                const double y = Y[r * R + c];
+                acc += y * y;
+            }
+        }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < R) {
+        double t = 0.0;
+        for (int k = 0; k < Q; ++k) t += red[k * R + tid];
+        part[(int64_t)blockIdx.x * R + tid] = t;
+    }
+}
+
+// lambda_j = sqrt(sum_k Y(k, j)^2)
+__global__ void k_norms(const double *__restrict__ sq, int R, double *__restrict__ lambda) {
+    for (int c = threadIdx.x; c < R; c += blockDim.x) lambda[c] = sqrt(sq[c]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -411,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_final(const double *__restrict_
 // lane layout of the model-value pass: 8 lanes per entry with up to 8 columns each (wide
 // loads, a 3-step group reduction), else one column per lane
 static void model_layout(int R, int *G, int *CPL) {
-    const int opts[] = {8, 4, 2, 1};
+    const int opts[] = {1, 2, 4, 8};  // fewest columns per lane that cover R with 8 lanes
     for (int c : opts)
         if (R % c == 0 && R / c <= 8) {
             *G = 8;
@@ -479,9 +608,9 @@ static int64_t max_dim(const spt_tensor *X) {
     return m;
 }
 
-// partial Grams per call: one per CU-ish, each workgroup covering many 64-row tiles, so the
-// final (sequential, deterministic) sum over partials stays short
-constexpr int kGramBlocks = 256;
+// partial Grams per call: up to four workgroups per CU, each covering many 64-row tiles; the
+// partials are then summed per entry by one wavefront in a fixed order
+constexpr int kGramBlocks = 1024;
 static int gram_blocks(int64_t I) {
     int64_t b = ceil_div(I, kGramRows);
     if (b > kGramBlocks) b = kGramBlocks;
@@ -492,10 +621,17 @@ template <class FT, bool NORM>
 static int launch_gram(const FT *Ain, const double *Y, const double *lambda, FT *Aout, int64_t I,
                        int R, double *gpart, double *G, hipStream_t s) {
     const int nb = gram_blocks(I);
-    hipLaunchKernelGGL((k_gram_partial<FT, NORM>), dim3(nb), dim3(kBlock), 0, s, Ain, Y, lambda,
-                       Aout, I, R, gpart);
-    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)ceil_div(R * R, kBlock)), dim3(kBlock), 0, s,
-                       gpart, nb, R * R, G);
+    if (R <= 16)
+        hipLaunchKernelGGL((k_gram_partial<FT, NORM, 1>), dim3(nb), dim3(kBlock), 0, s, Ain, Y,
+                           lambda, Aout, I, R, gpart);
+    else if (R <= 32)
+        hipLaunchKernelGGL((k_gram_partial<FT, NORM, 2>), dim3(nb), dim3(kBlock), 0, s, Ain, Y,
+                           lambda, Aout, I, R, gpart);
+    else
+        hipLaunchKernelGGL((k_gram_partial<FT, NORM, 4>), dim3(nb), dim3(kBlock), 0, s, Ain, Y,
+                           lambda, Aout, I, R, gpart);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)ceil_div(R * R, kBlock / kWave)), dim3(kBlock), 0,
+                       s, gpart, nb, R * R, G);
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }
 
@@ -516,17 +652,24 @@ static int gram_any(int fdtype, const void *Ain, const double *Y, const double *
     }
 }
 
-template <class VT>
-static int launch_solve(const VT *V, int64_t I, int R, const double *L, double *Y, hipStream_t s) {
-    int64_t nb = ceil_div(I, kBlock);
-    if (nb > 4096) nb = 4096;
+template <class VT, bool VEC>
+static void launch_solve_v(const VT *V, int64_t I, int R, const double *L, double *Y, hipStream_t s) {
+    int64_t nb = ceil_div(I, (int64_t)kBlock * (R <= 32 ? 2 : 1));  // every row in one pass
     if (nb < 1) nb = 1;
     if (R <= 16)
-        hipLaunchKernelGGL((k_solve_rows<16, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
+        hipLaunchKernelGGL((k_solve_rows<16, 2, VEC, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
     else if (R <= 32)
-        hipLaunchKernelGGL((k_solve_rows<32, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
+        hipLaunchKernelGGL((k_solve_rows<32, 2, VEC, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
     else
-        hipLaunchKernelGGL((k_solve_rows<64, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
+        hipLaunchKernelGGL((k_solve_rows<64, 1, VEC, VT>), dim3((unsigned)nb), dim3(kBlock), 0, s, V, I, R, L, Y);
+}
+
+template <class VT>
+static int launch_solve(const VT *V, int64_t I, int R, const double *L, double *Y, hipStream_t s) {
+    if (R % 4 == 0)
+        launch_solve_v<VT, true>(V, I, R, L, Y, s);
+    else
+        launch_solve_v<VT, false>(V, I, R, L, Y, s);
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }
 
@@ -587,11 +730,16 @@ int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fd
     rc = (fdtype == SPT_F64) ? launch_solve<double>((const double *)V, I, R, Lf, Y, s)
                              : launch_solve<float>((const float *)V, I, R, Lf, Y, s);
     if (rc) return rc;
-    // column norms from the diagonal of Y^T Y (the Gram routine on the FP64 solution)
-    rc = launch_gram<double, false>(Y, nullptr, nullptr, nullptr, I, R, gpart, GY, s);
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_norms_from_gram, dim3(1), dim3(64), 0, s, GY, R, lambda);
-    SPT_LAUNCH_CHECK();
+    // column 2-norms of the FP64 solution
+    {
+        int64_t nb = ceil_div(I, (int64_t)kGramRows);
+        if (nb > kMaxPartBlocks) nb = kMaxPartBlocks;
+        hipLaunchKernelGGL(k_colsq_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, Y, I, R, gpart);
+        hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)ceil_div(R, kBlock / kWave)), dim3(kBlock), 0, s,
+                           gpart, (int)nb, R, GY);
+        hipLaunchKernelGGL(k_norms, dim3(1), dim3(64), 0, s, GY, R, lambda);
+        SPT_LAUNCH_CHECK();
+    }
     return gram_any(fdtype, nullptr, Y, lambda, factors[mode], I, R, gpart,
                     grams + (size_t)mode * R * R, true, s);
 }
