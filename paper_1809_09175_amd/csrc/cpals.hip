@@ -577,10 +577,7 @@ static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
         SPT_MODEL_CFG(8, 4)
         SPT_MODEL_CFG(8, 8)
         SPT_MODEL_CFG(16, 1)
-        SPT_MODEL_CFG(16, 2)
-        SPT_MODEL_CFG(16, 4)
         SPT_MODEL_CFG(32, 1)
-        SPT_MODEL_CFG(32, 2)
         SPT_MODEL_CFG(64, 1)
         default: return SPT_EUNSUPPORTED;
     }

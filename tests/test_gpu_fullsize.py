@@ -1,0 +1,126 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark times (default
+layouts, mode-sorted record copies, the "auto" algorithm).  What the oracle can compute row by
+row is compared row by row: the rows of V (or of a gradient) fed by the entries whose mode-n
+subscript is one of the selected rows.  Selected rows: the heaviest row of each mode plus a
+ragged set of random rows.  The GCP loss is compared whole."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1809_09175_amd import datagen
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / (nb if nb > 0 else 1.0)
+
+
+def _rows(X, n, count, seed):
+    counts = np.bincount(X.subs[:, n], minlength=X.dims[n])
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[int(np.argmax(counts))],
+                                     rng.integers(0, X.dims[n], size=count)]))
+
+
+def _entries_of(X, n, rows):
+    mask = np.isin(X.subs[:, n], rows)
+    return X.subs[mask], X.vals[mask]
+
+
+def _device_tensor(X):
+    import paper_1809_09175_amd as spt
+    T = spt.SparseTensor(torch.from_numpy(X.subs).cuda(), torch.from_numpy(X.vals).cuda(), X.dims)
+    T.validate()
+    T.permute()
+    T.sort_copy()
+    return T
+
+
+def test_skewed4_full_size_bf16_and_fp32(gpu):
+    """4-way 1e6 x 1e5 x 1e4 x 365 tensor, 5e7 entries, R = 32: FP32 factors to 1e-5, BF16
+    factors to 2e-2 against the oracle on the unrounded factors, every mode."""
+    import paper_1809_09175_amd as spt
+    _log("skewed4 full size: generating")
+    X = datagen.skewed4()
+    T = _device_tensor(X)
+    R = 32
+    a32 = [a.astype(np.float32) for a in datagen.factors(X.dims, R, 11, np.float64)]
+    ref = [a.astype(np.float64) for a in a32]
+    dev32 = [torch.from_numpy(a).cuda() for a in a32]
+    devbf = [t.to(torch.bfloat16) for t in dev32]
+    for n in range(X.d):
+        rows = _rows(X, n, 30, seed=n)
+        s, v = _entries_of(X, n, rows)
+        V_ref = oracle.mttkrp(s, v, X.dims, ref, n)[rows]
+        for name, dev, tol in (("f32", dev32, 1e-5), ("bf16", devbf, 2e-2)):
+            _log(f"skewed4 mode {n} {name}")
+            V = spt.mttkrp(T, dev, n)
+            torch.cuda.synchronize()
+            got = V[torch.from_numpy(rows).cuda()].cpu().numpy()
+            assert _relerr(got, V_ref) < tol, (n, name)
+
+
+def test_gcp_counts_full_size(gpu):
+    """Count tensor 2e5 x 1e5 x 5e3 with 5e7 nonzeros and 5e7 sampled zeros, R = 32, Poisson
+    log link: the whole loss against the oracle's FP64 loss, and selected gradient rows of every
+    mode against the oracle's gradient over the entries that feed them."""
+    import paper_1809_09175_amd as spt
+    _log("gcp_counts full size: generating")
+    X, A = datagen.gcp_counts(R=32)
+    T = _device_tensor(X)
+    facs = [torch.from_numpy(a).cuda().requires_grad_(True) for a in A]
+    loss = spt.GCPPoissonLoss.apply(T, None, *facs)
+    loss.backward()
+    torch.cuda.synchronize()
+    ref = [a.astype(np.float64) for a in A]
+    _log("gcp_counts: oracle loss")
+    loss_ref = oracle.gcp(X.subs, X.vals, X.dims, ref, grads=False)
+    assert abs(loss.item() - loss_ref) < 1e-5 * abs(loss_ref)
+    for n in range(X.d):
+        rows = _rows(X, n, 20, seed=10 + n)
+        s, v = _entries_of(X, n, rows)
+        _, g_ref = oracle.gcp(s, v, X.dims, ref)
+        got = facs[n].grad[torch.from_numpy(rows).cuda()].cpu().numpy()
+        assert _relerr(got, g_ref[n][rows]) < 1e-4, n
+
+
+def test_batch64_full_size(gpu):
+    """All 64 tensors x 3 modes in one graph-replayed persistent launch with autotuned
+    per-product layouts: every output against the oracle, on two replays."""
+    import paper_1809_09175_amd as spt
+    _log("batch64 full size: generating")
+    Xs = datagen.batch64()
+    items, refs, keep = [], [], []
+    for t, X in enumerate(Xs):
+        T = _device_tensor(X)
+        R = X.meta["R"]
+        a32 = [a.astype(np.float32) for a in datagen.factors(X.dims, R, 400 + t, np.float64)]
+        dev = [torch.from_numpy(a).cuda() for a in a32]
+        keep.append((T, dev))
+        for n in range(3):
+            out = torch.empty((X.dims[n], R), device="cuda")
+            tune = spt.autotune(T, dev, n, batch=True, reps=1, out=out)
+            items.append({"X": T, "mode": n, "factors": dev, "out": out, "tune": tune})
+            refs.append(oracle.mttkrp(X.subs, X.vals, X.dims, [a.astype(np.float64) for a in a32], n))
+    B = spt.Batch(items)
+    for rep in range(2):
+        for it in items:
+            it["out"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        B.launch()
+        torch.cuda.synchronize()
+        for i, (it, ref) in enumerate(zip(items, refs)):
+            got = it["out"].cpu().numpy()
+            assert np.isfinite(got).all(), (rep, i)
+            assert _relerr(got, ref) < 1e-5, (rep, i, it["tune"])
+    B.close()
