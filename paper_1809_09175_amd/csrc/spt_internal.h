@@ -40,8 +40,10 @@ namespace spt {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;            // 4 waves
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kBlock * kSortItems;
+constexpr int kSortItems = 8;                       // keys per thread and sub-tile
+constexpr int kSortSub = kBlock * kSortItems;        // elements of one sub-tile
+constexpr int kSortSubs = 4;                         // sub-tiles one workgroup walks in order
+constexpr int kSortTile = kSortSub * kSortSubs;      // elements per workgroup (one digit-count column)
 constexpr int kScanSeg = kBlock * 8;
 constexpr int kRedSlots = 8192;
 

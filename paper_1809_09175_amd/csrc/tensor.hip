@@ -81,13 +81,29 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *__restrict
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int lane = threadIdx.x & 63;
+    for (int sub = 0; sub < kSortSubs; ++sub) {
+        const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)sub * kSortSub;
+        uint32_t dgs[kSortItems];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        int64_t e = base + it * kBlock + threadIdx.x;
-        if (e < P) {
-            uint32_t dg = ((uint32_t)sort_key<FIRST>(keys, recw, rw, n, e) >> shift) & 255u;
-            atomicAdd(&h[dg], 1u);
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t e = base + it * kBlock + threadIdx.x;
+            dgs[it] = (e < P) ? (((uint32_t)sort_key<FIRST>(keys, recw, rw, n, e) >> shift) & 255u) : 256u;
+        }
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            // lanes holding the same digit are matched with eight ballots; only the lowest of them
+            // adds the group's count, so a skewed digit costs one LDS atomic per wave, not 64
+            const uint32_t dg = dgs[it];
+            uint64_t m = __ballot(dg < 256u);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (dg >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            if (dg < 256u && (__ffsll((unsigned long long)m) - 1) == lane)
+                atomicAdd(&h[dg], (uint32_t)__popcll(m));
         }
     }
     __syncthreads();
@@ -160,7 +176,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t *__restrict__ a, 
     }
 }
 
-// Stable scatter of one tile: element order inside the tile is (item, wave, lane).
+// Stable scatter of one workgroup's tile: its sub-tiles in order, and inside a sub-tile the
+// element order (item, wave, lane).  gofs[d] is the next output position of digit d.  Each
+// sub-tile is first ordered by digit in LDS, then written out with consecutive threads on
+// consecutive positions of a digit's run, so the stores coalesce.
 template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const int32_t *__restrict__ keys, const int32_t *__restrict__ vals,
@@ -169,59 +188,75 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     int32_t *__restrict__ ovals) {
     __shared__ uint16_t cnt[kSortItems][kBlock / kWave][256];
     __shared__ uint32_t gofs[256];
+    __shared__ uint32_t tstart[256];
+    __shared__ int32_t lkey[kSortSub];
+    __shared__ int32_t lval[kSortSub];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    {
-        uint32_t *c32 = reinterpret_cast<uint32_t *>(&cnt[0][0][0]);
-        for (int k = tid; k < kSortItems * (kBlock / kWave) * 128; k += kBlock) c32[k] = 0;
-        gofs[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x];
-    }
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    int32_t k_[kSortItems], v_[kSortItems];
-    uint32_t dg_[kSortItems];
-    uint16_t rk_[kSortItems];
+    gofs[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        int64_t e = base + it * kBlock + tid;
-        bool valid = e < P;
-        int32_t key = valid ? sort_key<FIRST>(keys, recw, rw, n, e) : 0;
-        int32_t val = 0;
-        if (valid) val = FIRST ? (int32_t)e : vals[e];
-        uint32_t dg = ((uint32_t)key >> shift) & 255u;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            bool bit = (dg >> b) & 1u;
-            uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+    for (int sub = 0; sub < kSortSubs; ++sub) {
+        const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)sub * kSortSub;
+        if (base >= P) break;  // uniform
+        {
+            uint32_t *c32 = reinterpret_cast<uint32_t *>(&cnt[0][0][0]);
+            for (int k = tid; k < kSortItems * (kBlock / kWave) * 128; k += kBlock) c32[k] = 0;
         }
-        rk_[it] = (uint16_t)__popcll(m & lt);
-        if (valid && (__ffsll((unsigned long long)m) - 1) == lane)
-            cnt[it][wave][dg] = (uint16_t)__popcll(m);
-        k_[it] = key;
-        v_[it] = val;
-        dg_[it] = valid ? dg : 256u;
-    }
-    __syncthreads();
-    {   // per digit: exclusive prefix over (item, wave) in element order
-        uint32_t run = 0;
+        __syncthreads();
+        int32_t k_[kSortItems], v_[kSortItems];
+        uint32_t dg_[kSortItems];
+        uint16_t rk_[kSortItems];
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            int64_t e = base + it * kBlock + tid;
+            bool valid = e < P;
+            int32_t key = valid ? sort_key<FIRST>(keys, recw, rw, n, e) : 0;
+            int32_t val = 0;
+            if (valid) val = FIRST ? (int32_t)e : vals[e];
+            uint32_t dg = ((uint32_t)key >> shift) & 255u;
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                bool bit = (dg >> b) & 1u;
+                uint64_t bb = __ballot(bit);
+                m &= bit ? bb : ~bb;
+            }
+            rk_[it] = (uint16_t)__popcll(m & lt);
+            if (valid && (__ffsll((unsigned long long)m) - 1) == lane)
+                cnt[it][wave][dg] = (uint16_t)__popcll(m);
+            k_[it] = key;
+            v_[it] = val;
+            dg_[it] = valid ? dg : 256u;
+        }
+        __syncthreads();
+        uint32_t run = 0;  // per digit: exclusive prefix over (item, wave) in element order
         for (int it = 0; it < kSortItems; ++it)
             for (int w = 0; w < kBlock / kWave; ++w) {
                 uint32_t c = cnt[it][w][tid];
                 cnt[it][w][tid] = (uint16_t)run;
                 run += c;
             }
-    }
-    __syncthreads();
+        uint32_t all;
+        tstart[tid] = block_exclusive_scan(run, &all);  // sub-tile start of digit tid
+        __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        uint32_t dg = dg_[it];
-        if (dg < 256u) {
-            uint32_t dst = gofs[dg] + cnt[it][wave][dg] + rk_[it];
-            okeys[dst] = k_[it];
-            ovals[dst] = v_[it];
+        for (int it = 0; it < kSortItems; ++it) {
+            uint32_t dg = dg_[it];
+            if (dg < 256u) {
+                const uint32_t lp = tstart[dg] + cnt[it][wave][dg] + rk_[it];
+                lkey[lp] = k_[it];
+                lval[lp] = v_[it];
+            }
         }
+        __syncthreads();
+        for (uint32_t i = tid; i < all; i += kBlock) {
+            const int32_t key = lkey[i];
+            const uint32_t dg = ((uint32_t)key >> shift) & 255u;
+            const uint32_t dst = gofs[dg] + (i - tstart[dg]);
+            okeys[dst] = key;
+            ovals[dst] = lval[i];
+        }
+        __syncthreads();
+        gofs[tid] += run;  // this sub-tile's count of digit tid
     }
 }
 
