@@ -168,6 +168,9 @@ def bench_batch64(spt, datagen, torch, dev, reps=10):
     tuned_ms = timed(lambda: run_separate(True))
     B = spt.Batch([{k: it[k] for k in ("X", "mode", "factors", "out", "tune")} for it in items])
     batch_ms = timed(B.launch)
+    Bd = spt.Batch([{k: it[k] for k in ("X", "mode", "factors", "out")} for it in items])
+    batch_default_ms = timed(Bd.launch)
+    Bd.close()
     model = sum(it["nnz"] * model_bytes(3, it["R"]) for it in items)
     algos = {}
     for it in items:
@@ -176,6 +179,7 @@ def bench_batch64(spt, datagen, torch, dev, reps=10):
     res = {"products": len(items), "entries_total": int(sum(x.nnz for x in Xs)),
            "separate_default_ms": round(plain_ms, 3), "separate_tuned_ms": round(tuned_ms, 3),
            "batched_graph_ms": round(batch_ms, 3),
+           "batched_graph_default_layouts_ms": round(batch_default_ms, 3),
            "batched_speedup_vs_separate_default": round(plain_ms / batch_ms, 3),
            "batched_speedup_vs_separate_tuned": round(tuned_ms / batch_ms, 3),
            "batched_model_gbs": round(model / (batch_ms * 1e-3) / 1e9, 1),
