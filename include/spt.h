@@ -295,6 +295,26 @@ int spt_gcp_backward(const spt_tensor *X, int R, const void *const *factors, int
                      int loss_kind, const void *w, const void *m, const double *gscale, void *y,
                      void *const *grads, const spt_tune *tune, void *stream);
 
+/* Fused forward and backward of the generalized-CP loss with unit weights: for every mode n one
+ * pass over the entries in mode-n order (the sorted record copy if built, else the records
+ * gathered through the permutation) computes each entry's model value m_i, the derivative
+ * y_i = df/dm(x_i, m_i) and y_i's contribution to grads[n] = MTTKRP(Y, A, n), with the permuted
+ * MTTKRP's segmented reduction; the derivative tensor is never stored.  The pass over mode 0
+ * also sums the loss into *loss (device double; FP64 partials per wave chunk, summed in a fixed
+ * order).  grads are scaled by *gscale (device double) when gscale != NULL.  Same losses, types
+ * and factor layout as spt_gcp_forward; every mode must be permuted (else SPT_ESTATE); tune (or
+ * NULL) supplies lanes/cols/chunk, its algorithm is ignored; SPT_TUNE_DETERMINISTIC is not
+ * supported.  Uses the tensor's internal reduction scratch: calls on one tensor must not
+ * overlap.  Asynchronous on `stream`. */
+int spt_gcp_fused(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                  int loss_kind, double *loss, void *const *grads, const double *gscale,
+                  const spt_tune *tune, void *stream);
+
+/* dst[i] = src[i] * (*g) for n values (dtype SPT_F32 or SPT_F64; src may equal dst; g a device
+ * double): the upstream-gradient scaling of a loss computed before its gradient was requested. */
+int spt_scale_values(const void *src, void *dst, int64_t n, int dtype, const double *g,
+                     void *stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Precision and measurement helpers
  * ------------------------------------------------------------------------------------------- */

@@ -309,10 +309,16 @@ class GCPLoss(torch.autograd.Function):
       "poisson"   exp(m) - x m         (count data, log link)
       "bernoulli" log(1 + exp(m)) - x m (binary data, logit link)
       "gaussian"  (x - m)^2
-    Forward and backward run in libspt; the backward is one MTTKRP per mode of the derivative
-    tensor y_i = w_i df/dm(x_i, m_i).
+    Forward and backward run in libspt; the gradient is one MTTKRP per mode of the derivative
+    tensor y_i = w_i df/dm(x_i, m_i).  With unit weights (w None) and every mode permuted, the
+    forward runs the fused passes (spt_gcp_fused: loss and gradients in one sorted-order pass
+    per mode) and the backward only scales the stored gradients by the upstream gradient;
+    otherwise the forward computes the model values and loss and the backward the derivative
+    tensor and its MTTKRPs.  Setting GCPLoss.use_fused = False forces the second form.
 
     Usage: loss = GCPLoss.apply(X, w, "bernoulli", *factors)   (w may be None)."""
+
+    use_fused = True
 
     @staticmethod
     def forward(ctx, X, w, loss_kind, *factors):
@@ -324,6 +330,20 @@ class GCPLoss(torch.autograd.Function):
         R = int(factors[0].shape[1])
         vdt = torch.float64 if fd == SPT_F64 else torch.float32
         facs = [f.detach().contiguous() for f in factors]
+        ctx.fused_grads = None
+        if GCPLoss.use_fused and w is None:
+            loss = torch.empty((), dtype=torch.float64, device=X.device)
+            grads = [torch.empty_like(f) for f in facs]
+            rc = lib.spt_gcp_fused(X.handle, R, _factor_ptrs(facs), fd, kind,
+                                   ctypes.c_void_p(loss.data_ptr()),
+                                   _lib.ptr_array([t.data_ptr() for t in grads]), None, None,
+                                   _stream())
+            if rc == 0:
+                ctx.fused_grads = grads
+                ctx.fd = fd
+                return loss
+            if rc != _lib.SPT_ESTATE:
+                _lib.check(rc, "spt_gcp_fused")
         m = torch.empty(X.nnz, dtype=vdt, device=X.device)
         loss = torch.empty((), dtype=torch.float64, device=X.device)
         ws = torch.empty(32768, dtype=torch.uint8, device=X.device)
@@ -341,6 +361,16 @@ class GCPLoss(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gout):
+        if ctx.fused_grads is not None:
+            g = gout.detach().to(torch.float64).contiguous()
+            out = []
+            for t in ctx.fused_grads:
+                o = torch.empty_like(t)
+                _lib.check(_lib.load().spt_scale_values(
+                    ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(o.data_ptr()), t.numel(),
+                    ctx.fd, ctypes.c_void_p(g.data_ptr()), _stream()), "spt_scale_values")
+                out.append(o)
+            return (None, None, None, *out)
         m, *facs = ctx.saved_tensors
         X = ctx.X
         R = int(facs[0].shape[1])

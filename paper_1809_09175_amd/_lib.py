@@ -75,6 +75,8 @@ SIGNATURES = {
                                _c_p]),
     "spt_gcp_backward": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p,
                                 _c_p, _c_p]),
+    "spt_gcp_fused": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "spt_scale_values": (_c_i, [_c_p, _c_p, _c_i64, _c_i, _c_p, _c_p]),
     "spt_f32_to_bf16": (_c_i, [_c_p, _c_p, _c_i64, _c_p]),
     "spt_stream_triad": (_c_i, [_c_p, _c_p, _c_p, ctypes.c_float, _c_i64, _c_p]),
 }

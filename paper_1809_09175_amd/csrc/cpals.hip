@@ -371,12 +371,6 @@ __global__ void k_norms(const double *__restrict__ sq, int R, double *__restrict
 // ------------------------------------------------------------------------------------------
 enum { KIND_FIT = 0, KIND_VALUES = 1, KIND_GCP = 2 };
 
-// generalized CP elementwise losses (FP64): 0 Poisson log link, 1 Bernoulli logit, 2 Gaussian
-__device__ __forceinline__ double gcp_loss_term(int loss, double x, double m) {
-    if (loss == 0) return exp(m) - x * m;
-    if (loss == 1) return (m > 0.0 ? m : 0.0) + log1p(exp(-fabs(m))) - x * m;  // log(1 + e^m)
-    return (x - m) * (x - m);
-}
 
 // One entry of the model pass: x = its value, t = this lane's share of the model value,
 // sum_{j in lane} lambda_j prod_m A^(m)(l_m, j) (zero on lanes past column R, which still gather

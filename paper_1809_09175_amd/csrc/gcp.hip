@@ -10,13 +10,6 @@ int gcp_forward_impl(const spt_tensor *X, int R, const void *const *factors, int
                      int loss_kind, const void *w, void *m, double *loss, double *part,
                      hipStream_t s);
 
-// derivative of the elementwise loss with respect to the model value
-template <class T>
-__device__ __forceinline__ T gcp_dloss(int loss, T x, T m) {
-    if (loss == 0) return exp(m) - x;                       // Poisson, log link
-    if (loss == 1) return (T)1 / ((T)1 + exp(-m)) - x;      // Bernoulli, logit link
-    return (T)2 * (m - x);                                  // Gaussian
-}
 
 // y_i = g * w_i * df(x_i, m_i), g the upstream gradient (device scalar, NULL = 1)
 template <int RW, class T>

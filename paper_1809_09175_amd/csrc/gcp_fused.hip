@@ -1,0 +1,201 @@
+// Fused generalized-CP loss and gradient (Sec. 7 names generalized CP as the next workload).
+// One pass per mode n over the entries in mode-n order (the sorted record copy, or the records
+// gathered through the permutation) computes each entry's model value, the loss derivative y
+// and y's contribution to the mode-n gradient row, an MTTKRP of the derivative tensor with the
+// same segmented reduction as the permuted MTTKRP.  The derivative tensor is never written, and
+// the only gathers are the factor rows the MTTKRP reads anyway plus the mode-n row of the entry.
+// The pass over mode 0 also sums the loss.
+#include "mttkrp_kernels.h"
+
+namespace spt {
+
+template <int D, int G, int CPL, class FT>
+__global__ __launch_bounds__(kBlock) void k_gcp_fused(const int4 *__restrict__ rec,
+                                                      const int32_t *__restrict__ perm,
+                                                      const int4 *__restrict__ srec, int64_t P,
+                                                      int n, int R, FactorSet<FT> A,
+                                                      FT *__restrict__ V, int chunk, int loss,
+                                                      double *__restrict__ loss_part) {
+    __shared__ PermShared<D, G, CPL, FT, FT> sm[kBlock / kWave];
+    const int wave = threadIdx.x >> 6;
+    const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
+    if (c0 >= P) return;  // whole wavefront leaves together
+    perm_wave_chunk<D, G, CPL, FT, FT, FT, 64, true>(sm[wave], rec, perm, srec, P, n, R, A, nullptr,
+                                                     nullptr, V, chunk, c0, nullptr, nullptr, loss,
+                                                     loss_part);
+}
+
+// loss = sum of the per-wave partials: lane l adds partials l, l + 64, ... in order, then a
+// fixed butterfly (one wavefront, reproducible)
+__global__ __launch_bounds__(kWave) void k_sum_loss(const double *__restrict__ part, int64_t n,
+                                                    double *__restrict__ loss) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kWave) s += part[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) *loss = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_scale(const T *src, T *dst, int64_t n,
+                                                  const double *__restrict__ g) {
+    const T s = (T)*g;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i] * s;
+}
+
+struct FusedArgs {
+    const int4 *rec;
+    const int32_t *perm;
+    const int4 *srec;
+    int64_t P;
+    int n, R, chunk, loss;
+    void *V;
+    double *loss_part;
+    hipStream_t s;
+};
+
+template <int D, int G, int CPL, class FT>
+static int launch_fused_cfg(const FusedArgs &a, const FactorSet<FT> &A) {
+    const unsigned grid = (unsigned)ceil_div(a.P, (int64_t)a.chunk * (kBlock / kWave));
+    if (grid == 0) return SPT_OK;
+    hipLaunchKernelGGL((k_gcp_fused<D, G, CPL, FT>), dim3(grid), dim3(kBlock), 0, a.s, a.rec,
+                       a.perm, a.srec, a.P, a.n, a.R, A, static_cast<FT *>(a.V), a.chunk, a.loss,
+                       a.loss_part);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+template <int D, class FT>
+static int launch_fused_d(const FusedArgs &a, const FactorSet<FT> &A, int G, int CPL) {
+    switch (G * 16 + CPL) {
+        case 4 * 16 + 4: return launch_fused_cfg<D, 4, 4, FT>(a, A);
+        case 4 * 16 + 8: return launch_fused_cfg<D, 4, 8, FT>(a, A);
+        case 8 * 16 + 1: return launch_fused_cfg<D, 8, 1, FT>(a, A);
+        case 8 * 16 + 2: return launch_fused_cfg<D, 8, 2, FT>(a, A);
+        case 8 * 16 + 4: return launch_fused_cfg<D, 8, 4, FT>(a, A);
+        case 8 * 16 + 8: return launch_fused_cfg<D, 8, 8, FT>(a, A);
+        case 16 * 16 + 1: return launch_fused_cfg<D, 16, 1, FT>(a, A);
+        case 16 * 16 + 2: return launch_fused_cfg<D, 16, 2, FT>(a, A);
+        case 16 * 16 + 4: return launch_fused_cfg<D, 16, 4, FT>(a, A);
+        case 16 * 16 + 8: return launch_fused_cfg<D, 16, 8, FT>(a, A);
+        case 32 * 16 + 1: return launch_fused_cfg<D, 32, 1, FT>(a, A);
+        case 32 * 16 + 2: return launch_fused_cfg<D, 32, 2, FT>(a, A);
+        case 64 * 16 + 1: return launch_fused_cfg<D, 64, 1, FT>(a, A);
+        case 64 * 16 + 2: return launch_fused_cfg<D, 64, 2, FT>(a, A);
+        case 64 * 16 + 4: return launch_fused_cfg<D, 64, 4, FT>(a, A);
+        default: return SPT_EUNSUPPORTED;
+    }
+}
+
+template <class FT>
+static int launch_fused(const FusedArgs &a, int d, const void *const *factors, int G, int CPL) {
+    FactorSet<FT> A{};
+    for (int m = 0; m < d; ++m) A.p[m] = static_cast<const FT *>(factors[m]);
+    switch (d) {
+        case 2: return launch_fused_d<2, FT>(a, A, G, CPL);
+        case 3: return launch_fused_d<3, FT>(a, A, G, CPL);
+        case 4: return launch_fused_d<4, FT>(a, A, G, CPL);
+        case 5: return launch_fused_d<5, FT>(a, A, G, CPL);
+        default: return SPT_EUNSUPPORTED;
+    }
+}
+
+}  // namespace spt
+
+using namespace spt;
+
+extern "C" {
+
+int spt_gcp_fused(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                  int loss_kind, double *loss, void *const *grads, const double *gscale,
+                  const spt_tune *tune, void *stream) {
+    if (X == nullptr || R < 1 || R > 256 || loss == nullptr || grads == nullptr) return SPT_EINVAL;
+    if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAUSSIAN) return SPT_EINVAL;
+    if (fdtype == SPT_F64) {
+        if (X->vdtype != SPT_F64) return SPT_EUNSUPPORTED;
+    } else if (fdtype == SPT_F32) {
+        if (X->vdtype != SPT_F32) return SPT_EUNSUPPORTED;
+    } else {
+        return fdtype == SPT_BF16 ? SPT_EUNSUPPORTED : SPT_EINVAL;
+    }
+    int rc = check_factors(X, -1, factors);
+    if (rc) return rc;
+    for (int n = 0; n < X->d; ++n) {
+        if (grads[n] == nullptr) return SPT_EINVAL;
+        if (!X->permuted[n]) return SPT_ESTATE;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int at = (fdtype == SPT_F64) ? 8 : 4;
+    int64_t nparts = 0;
+    for (int n = 0; n < X->d; ++n) {
+        // the permuted layouts whatever algorithm the tune names (the pass is a permuted one)
+        spt_tune tin = tune ? *tune : spt_tune{0, 0, 0, 0, 0, 0}, t;
+        tin.algo = (X->srec[n] != nullptr) ? SPT_ALGO_PERMUTED_COPY : SPT_ALGO_PERMUTED;
+        if (tin.flags & SPT_TUNE_DETERMINISTIC) return SPT_EUNSUPPORTED;
+        rc = resolve_tune(X, n, R, fdtype, &tin, &t);
+        if (rc) return rc;
+        rc = zero_words(grads[n], X->dims[n] * (int64_t)R * at / 4, s);
+        if (rc) return rc;
+        if (X->P == 0) continue;
+        int64_t chunk = t.nnz_per_wave;
+        if (n == 0) {
+            // one loss partial per wave chunk, in the tensor's reduction scratch
+            const int64_t minc = (ceil_div(X->P, (int64_t)kRedSlots) + 63) / 64 * 64;
+            if (chunk < minc) chunk = minc;
+            nparts = ceil_div(X->P, chunk);
+        }
+        FusedArgs a;
+        a.rec = X->rec;
+        a.perm = X->perm[n];
+        a.srec = (t.algo == SPT_ALGO_PERMUTED_COPY) ? X->srec[n] : nullptr;
+        a.P = X->P;
+        a.n = n;
+        a.R = R;
+        a.chunk = (int)chunk;
+        a.loss = loss_kind;
+        a.V = grads[n];
+        a.loss_part = (n == 0) ? X->red : nullptr;
+        a.s = s;
+        rc = (fdtype == SPT_F64) ? launch_fused<double>(a, X->d, factors, t.lanes_per_nnz, t.cols_per_lane)
+                                 : launch_fused<float>(a, X->d, factors, t.lanes_per_nnz, t.cols_per_lane);
+        if (rc) return rc;
+        if (gscale != nullptr) {
+            const int64_t len = X->dims[n] * (int64_t)R;
+            int64_t blocks = ceil_div(len, kBlock);
+            if (blocks > 4096) blocks = 4096;
+            if (fdtype == SPT_F64)
+                hipLaunchKernelGGL(k_scale<double>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                                   static_cast<const double *>(grads[n]),
+                                   static_cast<double *>(grads[n]), len, gscale);
+            else
+                hipLaunchKernelGGL(k_scale<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                                   static_cast<const float *>(grads[n]),
+                                   static_cast<float *>(grads[n]), len, gscale);
+            SPT_LAUNCH_CHECK();
+        }
+    }
+    if (X->P == 0) return zero_words(loss, 2, s);
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(kWave), 0, s, X->red, nparts, loss);
+    SPT_LAUNCH_CHECK();
+    return SPT_OK;
+}
+
+int spt_scale_values(const void *src, void *dst, int64_t n, int dtype, const double *g,
+                     void *stream) {
+    if (n < 0 || g == nullptr || (n > 0 && (src == nullptr || dst == nullptr))) return SPT_EINVAL;
+    if (dtype != SPT_F32 && dtype != SPT_F64) return SPT_EINVAL;
+    if (n == 0) return SPT_OK;
+    int64_t blocks = ceil_div(n, kBlock);
+    if (blocks > 4096) blocks = 4096;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == SPT_F64)
+        hipLaunchKernelGGL(k_scale<double>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           static_cast<const double *>(src), static_cast<double *>(dst), n, g);
+    else
+        hipLaunchKernelGGL(k_scale<float>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           static_cast<const float *>(src), static_cast<float *>(dst), n, g);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+}  // extern "C"

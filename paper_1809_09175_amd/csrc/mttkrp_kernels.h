@@ -187,6 +187,65 @@ __device__ __forceinline__ void entry_product(const int *w, const OtherModes<D> 
     }
 }
 
+// Generalized CP elementwise losses f(x, m) (FP64) and their derivatives df/dm:
+// 0 Poisson with log link, 1 Bernoulli with logit link, 2 Gaussian.
+__device__ __forceinline__ double gcp_loss_term(int loss, double x, double m) {
+    if (loss == 0) return exp(m) - x * m;
+    if (loss == 1) return (m > 0.0 ? m : 0.0) + log1p(exp(-fabs(m))) - x * m;  // log(1 + e^m)
+    return (x - m) * (x - m);
+}
+
+template <class T>
+__device__ __forceinline__ T gcp_dloss(int loss, T x, T m) {
+    if (loss == 0) return exp(m) - x;                       // Poisson, log link
+    if (loss == 1) return (T)1 / ((T)1 + exp(-m)) - x;      // Bernoulli, logit link
+    return (T)2 * (m - x);                                  // Gaussian
+}
+
+// One entry of the fused generalized-CP pass over mode n: the model value
+// m = sum_j prod_m A^(m)(l_m, j) (product in mode order, this lane's columns summed, then a
+// butterfly over the G lanes of the group), y = df(x, m), and the gradient row contribution
+// t = y * prod_{m != n} A^(m)(l_m, j).  lterm receives f(x, m).  All lanes of the group must
+// take part (the butterfly); lanes past column R add nothing to m.
+template <int D, int RW, int G, int CPL, class FT, class AT>
+__device__ __forceinline__ void entry_gcp(const int *w, int key, const OtherModes<D> &om,
+                                          const char *anb, int n, uint32_t rowbytes,
+                                          uint32_t colbytes, bool colok, int loss, AT *t,
+                                          double &lterm) {
+    AT f[D - 1][CPL], an[CPL];
+#pragma unroll
+    for (int j = 0; j < D - 1; ++j) {
+        const int sub = (w[j] & ~om.up[j]) | (w[j + 1] & om.up[j]);
+        load_cols<FT, CPL, AT>(reinterpret_cast<const FT *>(om.base[j] + (uint32_t)sub * rowbytes + colbytes),
+                               f[j]);
+    }
+    load_cols<FT, CPL, AT>(reinterpret_cast<const FT *>(anb + (uint32_t)key * rowbytes + colbytes), an);
+    const AT x = rec_value<AT, RW>(w);
+    AT q = 0;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        AT p = 1;
+#pragma unroll
+        for (int j = 0; j < D - 1; ++j) {
+            p *= (j == n) ? an[c] : (AT)1;
+            p *= f[j][c];
+        }
+        p *= (n == D - 1) ? an[c] : (AT)1;
+        q += colok ? p : (AT)0;
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) q += __shfl_xor(q, o, G);
+    const AT y = gcp_dloss<AT>(loss, x, q);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        AT v = y;
+#pragma unroll
+        for (int j = 0; j < D - 1; ++j) v *= f[j][c];
+        t[c] = v;
+    }
+    lterm = gcp_loss_term(loss, (double)x, (double)q);
+}
+
 template <int RQ>
 __device__ __forceinline__ void lds_record(const int4 *q, int *w) {
     int4 a = q[0];
@@ -265,7 +324,10 @@ struct PermShared {
 };
 
 // One wavefront processes sorted positions [c0, min(c0 + chunk, P)) of mode n (c0 < P).
-template <int D, int G, int CPL, class FT, class VT, class AT, int UMAX = 64>
+// With GCP, the entries' values are replaced by the generalized-CP loss derivative computed on
+// the fly (entry_gcp; lambda and vovr unused), and when loss_part is given each wavefront also
+// writes the sum of its entries' loss terms to loss_part[c0 / chunk].
+template <int D, int G, int CPL, class FT, class VT, class AT, int UMAX = 64, bool GCP = false>
 __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &sm,
                                                 const int4 *__restrict__ rec,
                                                 const int32_t *__restrict__ perm,
@@ -275,7 +337,9 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                                                 const VT *__restrict__ vovr, AT *__restrict__ V,
                                                 int chunk, int64_t c0,
                                                 int *__restrict__ slot_keys = nullptr,
-                                                AT *__restrict__ slot_vals = nullptr) {
+                                                AT *__restrict__ slot_vals = nullptr,
+                                                int loss_kind = 0,
+                                                double *__restrict__ loss_part = nullptr) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int NG = kWave / G;
     constexpr int U0 = UnrollFor<KERNEL_PERM, G, CPL, FT>::value;
@@ -287,6 +351,9 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
     const uint32_t rowbytes = (uint32_t)R * sizeof(FT);
     const uint32_t colbytes = colok ? (uint32_t)col0 * sizeof(FT) : 0u;
     const OtherModes<D> om = other_modes<D>(A, n);
+    const char *anb = reinterpret_cast<const char *>(A.p[n]);
+    double lacc = 0.0;
+    (void)anb;
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
     const int S = chunk / NG;  // slice per group
     const int64_t gb = c0 + (int64_t)g * S;
@@ -366,7 +433,14 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                     int w[RW];
                     lds_record<RQ>(sr + (s0 + u) * RQ, w);
                     kk[u] = lds_sub<RW>(sr + (s0 + u) * RQ, n);
-                    entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
+                    if constexpr (GCP) {
+                        double lt;
+                        entry_gcp<D, RW, G, CPL, FT, AT>(w, kk[u], om, anb, n, rowbytes, colbytes,
+                                                         colok, loss_kind, t[u], lt);
+                        lacc += (gl == 0) ? lt : 0.0;
+                    } else {
+                        entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
+                    }
                 }
             } else {
 #pragma unroll
@@ -376,7 +450,14 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                         int w[RW];
                         lds_record<RQ>(sr + (s0 + u) * RQ, w);
                         kk[u] = lds_sub<RW>(sr + (s0 + u) * RQ, n);
-                        entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
+                        if constexpr (GCP) {
+                            double lt;
+                            entry_gcp<D, RW, G, CPL, FT, AT>(w, kk[u], om, anb, n, rowbytes,
+                                                             colbytes, colok, loss_kind, t[u], lt);
+                            lacc += (gl == 0) ? lt : 0.0;
+                        } else {
+                            entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
+                        }
                     }
                 }
             }
@@ -458,6 +539,14 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
             } else if (colok) {
                 atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, cacc);
             }
+        }
+    }
+    if constexpr (GCP) {
+        if (loss_part != nullptr) {
+            // lane sums in a fixed butterfly, one partial per wave chunk
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) lacc += __shfl_xor(lacc, o, 64);
+            if (lane == 0) loss_part[c0 / chunk] = lacc;
         }
     }
 }

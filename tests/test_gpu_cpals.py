@@ -6,6 +6,7 @@ workload stays below 4e-15 after 10 sweeps (the Hadamard Gram products there hav
 numbers 8..35), so FP64 factors, weights and Grams are held to 1e-11 and the fit to 1e-12.
 FP32 storage: one mode update maps the MTTKRP error (<= 1e-6 measured) through Gamma^-1, so
 factors are held to max(1e-5, 1e-6 cond(Gamma)).  BF16 storage adds one rounding of 2^-9."""
+import ctypes
 import itertools
 import sys
 
@@ -240,3 +241,97 @@ def test_gcp_general_losses(gpu, loss, kind):
     assert abs(L.item() - L_ref) < tol * abs(L_ref)
     for n in range(3):
         assert _relerr(facs[n].grad.cpu().numpy(), 0.5 * g_ref[n]) < gtol, n
+
+
+# ----------------------------------------------------------------------- fused GCP passes
+
+def _fused_case(dt, d, P, seed):
+    dims = (60, 45, 30, 20)[:d]
+    rng = np.random.default_rng(seed)
+    lin = rng.choice(int(np.prod(dims)), size=P, replace=False)
+    subs = np.stack(np.unravel_index(lin, dims), axis=1).astype(np.int32)
+    vals = rng.poisson(1.0, size=P).astype(dt)
+    A = [(rng.random((I, 6)) * 0.6).astype(dt) for I in dims]
+    return subs, vals, dims, A
+
+
+@pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian"])
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+@pytest.mark.parametrize("d,copies", [(3, False), (3, True), (4, True)])
+def test_gcp_fused_matches_oracle_and_unfused(gpu, loss, kind, d, copies):
+    """Fused loss-and-gradient passes (unit weights, permuted tensor) against the FP64 oracle,
+    and against the unfused forward/backward on the same factors."""
+    import paper_1809_09175_amd as spt
+    dt = np.float64 if kind == "f64" else np.float32
+    subs, vals, dims, A = _fused_case(dt, d, 5003, seed=d * 10 + len(loss))
+    if loss == "bernoulli":
+        vals = (vals > 0).astype(dt)
+    T = spt.SparseTensor(torch.from_numpy(subs).cuda(), torch.from_numpy(vals).cuda(), dims)
+    T.permute()
+    if copies:
+        T.sort_copy()
+    L_ref, g_ref = oracle.gcp(subs, vals, dims, [a.astype(np.float64) for a in A], loss)
+    tol, gtol = (1e-12, 1e-12) if kind == "f64" else (1e-5, 1e-4)
+    results = []
+    for fused in (True, False):
+        spt.GCPLoss.use_fused = fused
+        try:
+            facs = [torch.from_numpy(a).cuda().requires_grad_(True) for a in A]
+            L = spt.GCPLoss.apply(T, None, loss, *facs)
+            (0.5 * L).backward()
+            torch.cuda.synchronize()
+        finally:
+            spt.GCPLoss.use_fused = True
+        assert abs(L.item() - L_ref) < tol * abs(L_ref), fused
+        for n in range(d):
+            assert _relerr(facs[n].grad.cpu().numpy(), 0.5 * g_ref[n]) < gtol, (fused, n)
+        results.append((L.item(), [f.grad.cpu().numpy() for f in facs]))
+    assert abs(results[0][0] - results[1][0]) < tol * abs(L_ref)
+    for n in range(d):
+        assert _relerr(results[0][1][n], results[1][1][n]) < gtol, n
+
+
+def test_gcp_fused_gradcheck_fp64(gpu):
+    import paper_1809_09175_amd as spt
+    X, A = datagen.gcp_counts(scale=6e-7, dims=(9, 7, 5), R=3)
+    X.vals = X.vals.astype(np.float64)
+    T = _dev_tensor(X, np.float64)
+    T.permute()
+    facs = tuple(torch.from_numpy(a.astype(np.float64)).cuda().requires_grad_(True) for a in A)
+    assert torch.autograd.gradcheck(lambda *f: spt.GCPPoissonLoss.apply(T, None, *f), facs,
+                                    eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_gcp_fused_abi_edges(gpu):
+    """Through the C ABI: a tune with 64-entry wave chunks (the loss pass lengthens them so its
+    partials fit the tensor's scratch), ragged tiny tensors, the upstream scale, and the
+    refusal of an unpermuted tensor."""
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import _lib
+    lib = _lib.load()
+    for P, chunk in ((1, 0), (63, 0), (65, 64), (600_001, 64)):
+        dims = (700, 900, 1100)
+        rng = np.random.default_rng(P)
+        lin = np.unique(rng.integers(0, int(np.prod(dims)), size=P + P // 8 + 16))[:P]
+        assert lin.size == P
+        lin = lin[rng.permutation(P)]
+        subs = np.stack(np.unravel_index(lin, dims), axis=1).astype(np.int32)
+        vals = rng.poisson(1.5, size=P).astype(np.float32)
+        A = [(rng.random((I, 8)) * 0.5).astype(np.float32) for I in dims]
+        T = spt.SparseTensor(torch.from_numpy(subs).cuda(), torch.from_numpy(vals).cuda(), dims)
+        facs = [torch.from_numpy(a).cuda() for a in A]
+        grads = [torch.empty_like(f) for f in facs]
+        loss = torch.empty((), dtype=torch.float64, device="cuda")
+        g = torch.tensor(2.0, dtype=torch.float64, device="cuda")
+        tune = spt._tune("auto", 0, 0, chunk)
+        args = (T.handle, 8, spt._factor_ptrs(facs), _lib.SPT_F32, 0,
+                ctypes.c_void_p(loss.data_ptr()), _lib.ptr_array([t.data_ptr() for t in grads]),
+                ctypes.c_void_p(g.data_ptr()), ctypes.byref(tune), None)
+        assert lib.spt_gcp_fused(*args) == _lib.SPT_ESTATE
+        T.permute()
+        assert lib.spt_gcp_fused(*args) == 0
+        torch.cuda.synchronize()
+        L_ref, g_ref = oracle.gcp(subs, vals, dims, [a.astype(np.float64) for a in A])
+        assert abs(loss.item() - L_ref) < 1e-5 * abs(L_ref), P
+        for n in range(3):
+            assert _relerr(grads[n].cpu().numpy(), 2.0 * g_ref[n]) < 1e-4, (P, n)
