@@ -20,7 +20,10 @@ __global__ __launch_bounds__(kBlock) void k_gcp_fused(const int4 *__restrict__ r
     const int wave = threadIdx.x >> 6;
     const int64_t c0 = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * chunk;
     if (c0 >= P) return;  // whole wavefront leaves together
-    perm_wave_chunk<D, G, CPL, FT, FT, FT, 64, true>(sm[wave], rec, perm, srec, P, n, R, A, nullptr,
+    // one entry at a time per lane group: the fused entry holds d factor rows and the model
+    // butterfly, and deeper unrolling cost occupancy (1e8 entries, R = 32: 9.7 ms for the three
+    // passes against 11.7-15.9 ms with 2-8 entries in flight)
+    perm_wave_chunk<D, G, CPL, FT, FT, FT, 1, true>(sm[wave], rec, perm, srec, P, n, R, A, nullptr,
                                                      nullptr, V, chunk, c0, nullptr, nullptr, loss,
                                                      loss_part);
 }
