@@ -391,6 +391,10 @@ def main():
         extras["cp_fit_ms"] = round(fit_ms, 3)
         extras["sort_ms_all_modes"] = round(sort_ms, 3)
         extras["sorted_copy_ms_all_modes"] = round(copy_ms, 3)
+        # memory side of the trade: one record array per mode beside the records themselves
+        lib = spt._lib.load()
+        extras["sorted_copy_bytes_all_modes"] = int(lib.spt_tensor_sorted_copy_bytes(T.handle, -1))
+        extras["tensor_workspace_bytes"] = int(T.ws.numel())
         extras["sort_over_cp_als_iteration"] = round(sort_ms / (sweep_ms + fit_ms), 3)
         extras["sort_and_copy_over_cp_als_iteration"] = round((sort_ms + copy_ms) / (sweep_ms + fit_ms), 3)
         log(f"CP-ALS sweep {sweep_ms:.2f} ms, fit {fit_ms:.2f} ms")

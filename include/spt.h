@@ -286,8 +286,10 @@ int spt_gcp_poisson_backward(const spt_tensor *X, int R, const void *const *fact
  *   SPT_GCP_POISSON   f = exp(m) - x m,            df/dm = exp(m) - x
  *   SPT_GCP_BERNOULLI f = log(1 + exp(m)) - x m,   df/dm = 1 / (1 + exp(-m)) - x
  *   SPT_GCP_GAUSSIAN  f = (x - m)^2,               df/dm = 2 (m - x)
+ *   SPT_GCP_GAMMA     f = x / m' + log m',         df/dm = 1 / m' - x / m'^2,  m' = m + 1e-10
+ *                     (positive data, the model is the mean: factors must be nonnegative)
  * Arguments as for the Poisson calls; loss_kind outside these values gives SPT_EINVAL. */
-enum { SPT_GCP_POISSON = 0, SPT_GCP_BERNOULLI = 1, SPT_GCP_GAUSSIAN = 2 };
+enum { SPT_GCP_POISSON = 0, SPT_GCP_BERNOULLI = 1, SPT_GCP_GAUSSIAN = 2, SPT_GCP_GAMMA = 3 };
 int spt_gcp_forward(const spt_tensor *X, int R, const void *const *factors, int fdtype,
                     int loss_kind, const void *w, void *m, double *loss, void *ws,
                     size_t ws_bytes, void *stream);

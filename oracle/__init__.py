@@ -189,12 +189,13 @@ def gcp_poisson(subs, vals, dims, factors, w=None, grads=True):
     return (loss.value, gs) if grads else loss.value
 
 
-GCP_LOSSES = {"poisson": 0, "bernoulli": 1, "gaussian": 2}
+GCP_LOSSES = {"poisson": 0, "bernoulli": 1, "gaussian": 2, "gamma": 3}
 
 
 def gcp(subs, vals, dims, factors, loss="poisson", w=None, grads=True):
     """Generalized CP loss (poisson: exp(m) - x m; bernoulli: log(1+exp(m)) - x m; gaussian:
-    (x - m)^2) over the stored entries, and its gradient (an MTTKRP per mode)."""
+    (x - m)^2; gamma: x / m + log m for m > 0) over the stored entries, and its gradient (an
+    MTTKRP per mode)."""
     t = _T(subs, vals, dims)
     R = int(np.asarray(factors[0]).shape[1])
     fs, arr = _factor_array(factors, t.dims, R)

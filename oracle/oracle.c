@@ -252,11 +252,16 @@ done:
 }
 
 /* elementwise loss and derivative of the generalized CP losses (plain definitions) */
+/* Gamma: the model is the mean, kept positive by the caller (nonnegative factors); the shift
+ * ORACLE_GAMMA_EPS guards m = 0 */
+#define ORACLE_GAMMA_EPS 1e-10
+
 static double gcp_f(int kind, double x, double m)
 {
     switch (kind) {
     case 0: return exp(m) - x * m;
     case 1: return log1p(exp(m)) - x * m;
+    case 3: return x / (m + ORACLE_GAMMA_EPS) + log(m + ORACLE_GAMMA_EPS);
     default: return (x - m) * (x - m);
     }
 }
@@ -266,6 +271,7 @@ static double gcp_df(int kind, double x, double m)
     switch (kind) {
     case 0: return exp(m) - x;
     case 1: return 1.0 / (1.0 + exp(-m)) - x;
+    case 3: return 1.0 / (m + ORACLE_GAMMA_EPS) - x / ((m + ORACLE_GAMMA_EPS) * (m + ORACLE_GAMMA_EPS));
     default: return 2.0 * (m - x);
     }
 }
@@ -277,7 +283,7 @@ int oracle_gcp(int d, const int64_t *dims, int64_t P, const int32_t *subs, const
     int rc = check_tensor(d, dims, P, subs);
     if (rc) return rc;
     if (R < 1 || A == NULL || loss == NULL || (P > 0 && vals == NULL) || loss_kind < 0 ||
-        loss_kind > 2)
+        loss_kind > 3)
         return ORACLE_EINVAL;
     double *m = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
     double *y = (double *)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));

@@ -77,6 +77,8 @@ int oracle_gcp_poisson(int d, const int64_t *dims, int64_t P, const int32_t *sub
  *   loss 0, Poisson with log link:  f = exp(m) - x m,          df = exp(m) - x
  *   loss 1, Bernoulli with logit:   f = log(1 + exp(m)) - x m,  df = 1 / (1 + exp(-m)) - x
  *   loss 2, Gaussian:               f = (x - m)^2,              df = 2 (m - x)
+ *   loss 3, Gamma (m > 0):          f = x / m' + log m',        df = 1 / m' - x / m'^2,
+ *                                   m' = m + 1e-10 (guards m = 0; factors nonnegative)
  * loss = sum_i w_i f(x_i, m_i), grad[n] = MTTKRP(Y, A, n) with y_i = w_i df(x_i, m_i). */
 int oracle_gcp(int d, const int64_t *dims, int64_t P, const int32_t *subs, const double *vals,
                const double *w, int R, const double *const *A, int loss_kind, double *loss,

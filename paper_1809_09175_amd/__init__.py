@@ -309,6 +309,7 @@ class GCPLoss(torch.autograd.Function):
       "poisson"   exp(m) - x m         (count data, log link)
       "bernoulli" log(1 + exp(m)) - x m (binary data, logit link)
       "gaussian"  (x - m)^2
+      "gamma"     x / m + log m         (positive data; nonnegative factors, m > 0)
     Forward and backward run in libspt; the gradient is one MTTKRP per mode of the derivative
     tensor y_i = w_i df/dm(x_i, m_i).  With unit weights (w None) and every mode permuted, the
     forward runs the fused passes (spt_gcp_fused: loss and gradients in one sorted-order pass

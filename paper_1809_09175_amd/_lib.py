@@ -31,7 +31,7 @@ class SptTune(ctypes.Structure):
 
 
 TUNE_DETERMINISTIC = 1
-GCP_LOSSES = {"poisson": 0, "bernoulli": 1, "gaussian": 2}
+GCP_LOSSES = {"poisson": 0, "bernoulli": 1, "gaussian": 2, "gamma": 3}
 
 
 # name -> (restype, argtypes); every symbol include/spt.h declares

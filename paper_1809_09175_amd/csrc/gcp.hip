@@ -58,7 +58,7 @@ int spt_gcp_forward(const spt_tensor *X, int R, const void *const *factors, int 
                     int loss_kind, const void *w, void *m, double *loss, void *ws,
                     size_t ws_bytes, void *stream) {
     if (X == nullptr || R < 1 || R > 64 || m == nullptr || loss == nullptr) return SPT_EINVAL;
-    if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAUSSIAN) return SPT_EINVAL;
+    if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAMMA) return SPT_EINVAL;
     if (int e = gcp_dtype_ok(X, fdtype)) return e;
     int rc = check_factors(X, -1, factors);
     if (rc) return rc;
@@ -80,7 +80,7 @@ int spt_gcp_backward(const spt_tensor *X, int R, const void *const *factors, int
                      void *const *grads, const spt_tune *tune, void *stream) {
     if (X == nullptr || R < 1 || R > 256 || m == nullptr || y == nullptr || grads == nullptr)
         return SPT_EINVAL;
-    if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAUSSIAN) return SPT_EINVAL;
+    if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAMMA) return SPT_EINVAL;
     if (int e = gcp_dtype_ok(X, fdtype)) return e;
     int rc = check_factors(X, -1, factors);
     if (rc) return rc;

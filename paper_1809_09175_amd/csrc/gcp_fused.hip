@@ -114,7 +114,7 @@ int spt_gcp_fused(const spt_tensor *X, int R, const void *const *factors, int fd
                   int loss_kind, double *loss, void *const *grads, const double *gscale,
                   const spt_tune *tune, void *stream) {
     if (X == nullptr || R < 1 || R > 256 || loss == nullptr || grads == nullptr) return SPT_EINVAL;
-    if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAUSSIAN) return SPT_EINVAL;
+    if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAMMA) return SPT_EINVAL;
     if (fdtype == SPT_F64) {
         if (X->vdtype != SPT_F64) return SPT_EUNSUPPORTED;
     } else if (fdtype == SPT_F32) {

@@ -188,10 +188,14 @@ __device__ __forceinline__ void entry_product(const int *w, const OtherModes<D> 
 }
 
 // Generalized CP elementwise losses f(x, m) (FP64) and their derivatives df/dm:
-// 0 Poisson with log link, 1 Bernoulli with logit link, 2 Gaussian.
+// 0 Poisson with log link, 1 Bernoulli with logit link, 2 Gaussian, 3 Gamma (the model is the
+// positive mean; m + 1e-10 guards m = 0).
+constexpr double kGammaEps = 1e-10;
+
 __device__ __forceinline__ double gcp_loss_term(int loss, double x, double m) {
     if (loss == 0) return exp(m) - x * m;
     if (loss == 1) return (m > 0.0 ? m : 0.0) + log1p(exp(-fabs(m))) - x * m;  // log(1 + e^m)
+    if (loss == 3) return x / (m + kGammaEps) + log(m + kGammaEps);
     return (x - m) * (x - m);
 }
 
@@ -199,6 +203,10 @@ template <class T>
 __device__ __forceinline__ T gcp_dloss(int loss, T x, T m) {
     if (loss == 0) return exp(m) - x;                       // Poisson, log link
     if (loss == 1) return (T)1 / ((T)1 + exp(-m)) - x;      // Bernoulli, logit link
+    if (loss == 3) {                                        // Gamma
+        const T r = (T)1 / (m + (T)kGammaEps);
+        return r - x * r * r;
+    }
     return (T)2 * (m - x);                                  // Gaussian
 }
 

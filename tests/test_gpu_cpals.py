@@ -220,7 +220,7 @@ def test_gcp_gradcheck_fp64(gpu):
                                     eps=1e-6, atol=1e-7, rtol=1e-6)
 
 
-@pytest.mark.parametrize("loss", ["bernoulli", "gaussian", "poisson"])
+@pytest.mark.parametrize("loss", ["bernoulli", "gaussian", "poisson", "gamma"])
 @pytest.mark.parametrize("kind", ["f64", "f32"])
 def test_gcp_general_losses(gpu, loss, kind):
     import paper_1809_09175_amd as spt
@@ -232,10 +232,11 @@ def test_gcp_general_losses(gpu, loss, kind):
     T.permute()
     rng = np.random.default_rng(4)
     w = (rng.random(X.nnz) + 0.5).astype(dt)
-    facs = [torch.from_numpy(a - 0.2).cuda().requires_grad_(True) for a in A]
+    shift = 0.05 if loss == "gamma" else -0.2  # the Gamma model is a positive mean
+    facs = [torch.from_numpy(a + shift).cuda().requires_grad_(True) for a in A]
     L = spt.GCPLoss.apply(T, torch.from_numpy(w).cuda(), loss, *facs)
     (0.5 * L).backward()
-    L_ref, g_ref = oracle.gcp(X.subs, X.vals, X.dims, [a.astype(np.float64) - 0.2 for a in A],
+    L_ref, g_ref = oracle.gcp(X.subs, X.vals, X.dims, [a.astype(np.float64) + shift for a in A],
                               loss, w.astype(np.float64))
     tol, gtol = (1e-12, 1e-12) if kind == "f64" else (1e-5, 1e-4)
     assert abs(L.item() - L_ref) < tol * abs(L_ref)
@@ -251,11 +252,11 @@ def _fused_case(dt, d, P, seed):
     lin = rng.choice(int(np.prod(dims)), size=P, replace=False)
     subs = np.stack(np.unravel_index(lin, dims), axis=1).astype(np.int32)
     vals = rng.poisson(1.0, size=P).astype(dt)
-    A = [(rng.random((I, 6)) * 0.6).astype(dt) for I in dims]
+    A = [(rng.random((I, 6)) * 0.6 + 0.02).astype(dt) for I in dims]
     return subs, vals, dims, A
 
 
-@pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian"])
+@pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian", "gamma"])
 @pytest.mark.parametrize("kind", ["f64", "f32"])
 @pytest.mark.parametrize("d,copies", [(3, False), (3, True), (4, True)])
 def test_gcp_fused_matches_oracle_and_unfused(gpu, loss, kind, d, copies):

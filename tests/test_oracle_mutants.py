@@ -32,6 +32,9 @@ MUTANTS = [
     ("logit derivative", "case 1: return 1.0 / (1.0 + exp(-m)) - x;", "case 1: return 1.0 / (1.0 + exp(m)) - x;"),
     ("gaussian derivative factor", "default: return 2.0 * (m - x);", "default: return (m - x);"),
     ("gaussian loss sign", "default: return (x - m) * (x - m);", "default: return (x + m) * (x - m);"),
+    ("gamma derivative sign", "case 3: return 1.0 / (m + ORACLE_GAMMA_EPS) - x /",
+     "case 3: return 1.0 / (m + ORACLE_GAMMA_EPS) + x /"),
+    ("gamma loss log term", "+ log(m + ORACLE_GAMMA_EPS);", "- log(m + ORACLE_GAMMA_EPS);"),
     ("unstable perm", "for (int64_t i = 0; i < P; ++i) {\n        int32_t k = subs[i * d + n];",
      "for (int64_t i = P - 1; i >= 0; --i) {\n        int32_t k = subs[i * d + n];"),
     ("bf16 ties away", "? hi_bits : lo_bits; /* tie", "? lo_bits : hi_bits; /* tie"),
@@ -49,6 +52,7 @@ CHECKS = [
     (pins.test_gcp_poisson_loss_dense_and_gradient_finite_differences, {}),
     (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="bernoulli")),
     (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="gaussian")),
+    (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="gamma")),
     (pins.test_bf16_rne_matches_torch_on_samples_and_boundaries, {}),
 ]
 

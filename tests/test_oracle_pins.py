@@ -310,7 +310,7 @@ def test_bf16_rne_matches_torch_on_samples_and_boundaries():
     assert oracle.bf16_rne(np.array([0x7F7F0000], np.uint32))[0] == 0x7F7F
 
 
-@pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian"])
+@pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian", "gamma"])
 def test_gcp_losses_dense_and_finite_differences(loss):
     rng = np.random.default_rng(43)
     dims = (5, 4, 3)
@@ -319,11 +319,14 @@ def test_gcp_losses_dense_and_finite_differences(loss):
     vals = (rng.random(30) < 0.5).astype(np.float64) if loss == "bernoulli" else rng.random(30) * 3
     w = rng.random(30) + 0.5
     R = 2
-    A = [rng.random((I, R)) - 0.3 for I in dims]
+    # the Gamma model is a positive mean: nonnegative factors, kept away from m = 0
+    A = [rng.random((I, R)) + (0.2 if loss == "gamma" else -0.3) for I in dims]
     L, grads = oracle.gcp(subs, vals, dims, A, loss, w)
     M = np.einsum("ir,jr,kr->ijk", *A)[subs[:, 0], subs[:, 1], subs[:, 2]]
-    f = {"poisson": np.exp(M) - vals * M, "bernoulli": np.logaddexp(0.0, M) - vals * M,
-         "gaussian": (vals - M) ** 2}[loss]
+    f = {"poisson": lambda: np.exp(M) - vals * M,
+         "bernoulli": lambda: np.logaddexp(0.0, M) - vals * M,
+         "gaussian": lambda: (vals - M) ** 2,
+         "gamma": lambda: vals / (M + 1e-10) + np.log(M + 1e-10)}[loss]()
     assert abs(L - np.sum(w * f)) < 1e-12 * abs(L)
     if loss == "gaussian":
         # d/dA of sum w (x - m)^2 = MTTKRP of 2 w (m - x): check against a dense route
