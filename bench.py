@@ -260,10 +260,18 @@ def main():
     t0 = time.time()
     X = datagen.powerlaw3()
     log(f"generated powerlaw3 ({X.nnz} entries) in {time.time() - t0:.1f}s")
+    # ingest: host (pageable numpy) -> device copies, then packing into records
+    torch.empty(1, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
     subs = torch.from_numpy(X.subs).to(dev)
     vals = torch.from_numpy(X.vals).to(dev)
+    torch.cuda.synchronize()
+    h2d_ms = (time.time() - t0) * 1e3
+    t0 = time.time()
     T = spt.SparseTensor(subs, vals, X.dims)
     T.validate()
+    pack_ms = (time.time() - t0) * 1e3
     del subs, vals
 
     def timed(fn, reps=1):
@@ -391,6 +399,8 @@ def main():
         extras["cp_fit_ms"] = round(fit_ms, 3)
         extras["sort_ms_all_modes"] = round(sort_ms, 3)
         extras["sorted_copy_ms_all_modes"] = round(copy_ms, 3)
+        extras["ingest_h2d_ms"] = round(h2d_ms, 1)
+        extras["ingest_pack_validate_ms"] = round(pack_ms, 1)
         # memory side of the trade: one record array per mode beside the records themselves
         lib = spt._lib.load()
         extras["sorted_copy_bytes_all_modes"] = int(lib.spt_tensor_sorted_copy_bytes(T.handle, -1))
