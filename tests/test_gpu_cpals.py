@@ -44,12 +44,14 @@ def _np(t):
         else t.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("algo", ["atomic", "permuted"])
+@pytest.mark.parametrize("algo", ["atomic", "permuted", "permuted_copy"])
 def test_cpals_small_fp64_ten_sweeps(gpu, algo):
     import paper_1809_09175_amd as spt
     X, A = datagen.cpals_small()
     T = _dev_tensor(X, np.float64)
     T.permute()
+    if algo == "permuted_copy":
+        T.sort_copy()  # the fit then also runs over the sorted copy
     st = spt.CPState(T, [torch.from_numpy(a.copy()).cuda() for a in A])
     Ao = [a.copy() for a in A]
     lo = np.ones(16)
@@ -111,11 +113,17 @@ def test_cp_mode_update_low_precision(gpu, kind):
         assert _relerr(st.grams[n].cpu().numpy(), stored.T @ stored) < 1e-12
 
 
-def test_fit_matches_oracle_fp32_factors(gpu):
+@pytest.mark.parametrize("copy_mode", [None, 0, 2])
+def test_fit_matches_oracle_fp32_factors(gpu, copy_mode):
+    """Fit from FP32 factors: over the records in storage order, and over a sorted record copy
+    (mode 0 or 2) when one exists."""
     import paper_1809_09175_amd as spt
     X = _skewed4_small()
     R = 16
     T = _dev_tensor(X, np.float32)
+    if copy_mode is not None:
+        T.permute(copy_mode)
+        T.sort_copy(copy_mode)
     A32 = datagen.factors(X.dims, R, seed=9, dtype=np.float32)
     st = spt.CPState(T, [torch.from_numpy(a).cuda() for a in A32])
     st.lam = torch.linspace(0.5, 2.0, R, dtype=torch.float64, device="cuda")
