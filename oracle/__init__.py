@@ -211,6 +211,42 @@ def gcp(subs, vals, dims, factors, loss="poisson", w=None, grads=True):
     return (out.value, gs) if grads else out.value
 
 
+def philox4x64(ctr, key):
+    """Philox4x64-10 block: four uint64 words from a 4-word counter and a 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    if c.shape != (4,) or k.shape != (2,):
+        raise ValueError("counter must have 4 words, key 2")
+    out = np.empty(4, dtype=np.uint64)
+    _load().oracle_philox4x64(_p(c), _p(k), _p(out))
+    return out
+
+
+def gcp_sample(subs, vals, dims, seed, it, s_nz, s_z):
+    """Stratified GCP-SGD sample of iteration `it`: (subs (s_nz+s_z) x d, vals, weights)."""
+    t = _T(subs, vals, dims)
+    n = int(s_nz) + int(s_z)
+    os_ = np.empty((n, t.d), dtype=np.int32)
+    ov = np.empty(n, dtype=np.float64)
+    ow = np.empty(n, dtype=np.float64)
+    _check(_load().oracle_gcp_sample(*t.head(), _p(t.vals), ctypes.c_uint64(int(seed)),
+                                     ctypes.c_int64(int(it)), ctypes.c_int64(int(s_nz)),
+                                     ctypes.c_int64(int(s_z)), _p(os_), _p(ov), _p(ow)))
+    return os_, ov, ow
+
+
+def adam(x, g, m, v, lr, beta1, beta2, eps, t, lower=-np.inf):
+    """One Adam step in place on FP64 arrays x, m, v (g read)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, g, m, v)]
+    for a in (x, m, v):
+        if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
+            raise ValueError("x, m, v must be contiguous float64 arrays (updated in place)")
+    _check(_load().oracle_adam(ctypes.c_int64(x.size), _p(x), _p(arrs[1]), _p(m), _p(v),
+                               ctypes.c_double(lr), ctypes.c_double(beta1),
+                               ctypes.c_double(beta2), ctypes.c_double(eps),
+                               ctypes.c_int64(int(t)), ctypes.c_double(lower)))
+
+
 def bf16_rne(x):
     """FP32 array (or its uint32 bit patterns) -> uint16 BF16 bit patterns."""
     a = np.ascontiguousarray(x)

@@ -350,3 +350,94 @@ int oracle_bf16_rne_array(int64_t n, const uint32_t *in, uint16_t *out)
     for (int64_t i = 0; i < n; ++i) out[i] = oracle_bf16_rne(in[i]);
     return ORACLE_OK;
 }
+
+/* ---------------------------------------------------------------------------------------------
+ * Stochastic generalized CP (GCP-SGD; generalized CP is the workload Sec. 7 names next).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC'11): ten rounds of two 64x64->128 multiplications on a 4-word counter under a 2-word key
+ * bumped by the Weyl constants. */
+static void mul_hilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_hilo64(0xD2E7470EE14C6C93ull, c0, &hi0, &lo0);
+        mul_hilo64(0xCA5A826395121157ull, c2, &hi1, &lo1);
+        uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* floor(r * n / 2^64): a 64-bit random word mapped onto 0..n-1 */
+static int64_t scale_index(uint64_t r, int64_t n)
+{
+    return (int64_t)(((unsigned __int128)r * (unsigned __int128)(uint64_t)n) >> 64);
+}
+
+int oracle_gcp_sample(int d, const int64_t *dims, int64_t P, const int32_t *subs,
+                      const double *vals, uint64_t seed, int64_t iter, int64_t s_nz,
+                      int64_t s_z, int32_t *out_subs, double *out_vals, double *out_w)
+{
+    int rc = check_tensor(d, dims, P, subs);
+    if (rc) return rc;
+    if (s_nz < 0 || s_z < 0 || (s_nz > 0 && P == 0) || iter < 0 ||
+        (s_nz + s_z > 0 && (out_subs == NULL || out_vals == NULL || out_w == NULL)))
+        return ORACLE_EINVAL;
+    const uint64_t key[2] = {seed, 0};
+    double cells = 1.0;
+    for (int m = 0; m < d; ++m) cells *= (double)dims[m];
+    const double w_nz = s_nz > 0 ? (double)P / (double)s_nz : 0.0;
+    const double w_z = (s_z > 0 && cells > (double)P) ? (cells - (double)P) / (double)s_z : 0.0;
+    for (int64_t k = 0; k < s_nz; ++k) {
+        const uint64_t ctr[4] = {(uint64_t)k, (uint64_t)iter, 0, 0};
+        uint64_t r[4];
+        oracle_philox4x64(ctr, key, r);
+        const int64_t p = scale_index(r[0], P);
+        for (int m = 0; m < d; ++m) out_subs[k * d + m] = subs[p * d + m];
+        out_vals[k] = vals[p];
+        out_w[k] = w_nz;
+    }
+    for (int64_t k = 0; k < s_z; ++k) {
+        const int64_t e = s_nz + k;
+        uint64_t r[8];
+        const uint64_t c0[4] = {(uint64_t)k, (uint64_t)iter, 1, 0};
+        oracle_philox4x64(c0, key, r);
+        if (d > 4) {
+            const uint64_t c1[4] = {(uint64_t)k, (uint64_t)iter, 1, 1};
+            oracle_philox4x64(c1, key, r + 4);
+        }
+        for (int m = 0; m < d; ++m) out_subs[e * d + m] = (int32_t)scale_index(r[m], dims[m]);
+        out_vals[e] = 0.0;
+        out_w[e] = w_z;
+    }
+    return ORACLE_OK;
+}
+
+int oracle_adam(int64_t n, double *x, const double *g, double *m, double *v, double lr,
+                double beta1, double beta2, double eps, int64_t t, double lower)
+{
+    if (n < 0 || t < 1 || (n > 0 && (x == NULL || g == NULL || m == NULL || v == NULL)))
+        return ORACLE_EINVAL;
+    const double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
+        const double mh = m[i] / c1, vh = v[i] / c2;
+        double xi = x[i] - lr * mh / (sqrt(vh) + eps);
+        x[i] = xi < lower ? lower : xi;
+    }
+    return ORACLE_OK;
+}

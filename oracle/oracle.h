@@ -84,6 +84,26 @@ int oracle_gcp(int d, const int64_t *dims, int64_t P, const int32_t *subs, const
                const double *w, int R, const double *const *A, int loss_kind, double *loss,
                double *const *grads);
 
+/* Philox4x64-10 counter-based generator (Salmon et al., SC'11): out = philox(ctr, key). */
+void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Stratified sample for stochastic generalized CP, iteration iter, key (seed, 0):
+ *   entries 0..s_nz-1: stored entry p = floor(r0 * P / 2^64), r = philox((k, iter, 0, 0)),
+ *                      weight P / s_nz;
+ *   entries s_nz..s_nz+s_z-1 (k = 0..s_z-1): a uniform cell, subscript m = floor(r_m * I_m /
+ *                      2^64) with r = philox((k, iter, 1, 0)) (modes 4.. from (k, iter, 1, 1)),
+ *                      value 0, weight (prod I_m - P) / s_z.  Cells that hold a stored entry are
+ *                      not rejected (a bias of order P / prod I_m).
+ * out_subs: (s_nz + s_z) x d, out_vals and out_w: s_nz + s_z. */
+int oracle_gcp_sample(int d, const int64_t *dims, int64_t P, const int32_t *subs,
+                      const double *vals, uint64_t seed, int64_t iter, int64_t s_nz,
+                      int64_t s_z, int32_t *out_subs, double *out_vals, double *out_w);
+
+/* Adam step t >= 1 (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * x = max(lower, x - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)). */
+int oracle_adam(int64_t n, double *x, const double *g, double *m, double *v, double lr,
+                double beta1, double beta2, double eps, int64_t t, double lower);
+
 /* FP32 -> BF16 round to nearest, ties to even, by comparing the distances to the two
  * neighbouring BF16 values.  NaN maps to a quiet NaN with the same sign and top payload. */
 uint16_t oracle_bf16_rne(uint32_t f32_bits);

@@ -35,6 +35,9 @@ MUTANTS = [
     ("gamma derivative sign", "case 3: return 1.0 / (m + ORACLE_GAMMA_EPS) - x /",
      "case 3: return 1.0 / (m + ORACLE_GAMMA_EPS) + x /"),
     ("gamma loss log term", "+ log(m + ORACLE_GAMMA_EPS);", "- log(m + ORACLE_GAMMA_EPS);"),
+    ("philox key bump", "k1 += 0xBB67AE8584CAA73Bull;", "k1 += 0x9E3779B97F4A7C15ull;"),
+    ("zero-sample weight", "(cells - (double)P) / (double)s_z", "cells / (double)s_z"),
+    ("adam bias correction", "const double mh = m[i] / c1,", "const double mh = m[i],"),
     ("unstable perm", "for (int64_t i = 0; i < P; ++i) {\n        int32_t k = subs[i * d + n];",
      "for (int64_t i = P - 1; i >= 0; --i) {\n        int32_t k = subs[i * d + n];"),
     ("bf16 ties away", "? hi_bits : lo_bits; /* tie", "? lo_bits : hi_bits; /* tie"),
@@ -54,6 +57,9 @@ CHECKS = [
     (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="gaussian")),
     (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="gamma")),
     (pins.test_bf16_rne_matches_torch_on_samples_and_boundaries, {}),
+    (pins.test_philox_matches_numpy_philox, {}),
+    (pins.test_gcp_sample_is_unbiased_and_uniform, {}),
+    (pins.test_adam_constant_gradient_closed_form, {}),
 ]
 
 

@@ -344,3 +344,77 @@ def test_gcp_losses_dense_and_finite_differences(loss):
             fd = (oracle.gcp(subs, vals, dims, Ap, loss, w, grads=False)
                   - oracle.gcp(subs, vals, dims, Am, loss, w, grads=False)) / (2 * h)
             assert abs(fd - grads[n][k, j]) < 1e-7 * max(1.0, abs(fd))
+
+
+# ------------------------------------------------------------------ stochastic generalized CP
+
+def test_philox_matches_numpy_philox():
+    """The oracle's Philox4x64-10 block equals numpy's independent implementation of the
+    published generator (numpy advances its counter before each block)."""
+    for key, ctr in [((5, 0), (1, 0, 0, 0)), ((2**63 + 11, 77), (9, 3, 1, 0)),
+                     ((0, 0), (2**40, 2**33, 1, 1)), ((123456789, 0), (65537, 0, 0, 5))]:
+        bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                              counter=np.array((ctr[0] - 1,) + ctr[1:], dtype=np.uint64))
+        assert list(oracle.philox4x64(ctr, key)) == list(bg.random_raw(4)), (key, ctr)
+
+
+def test_gcp_sample_is_unbiased_and_uniform():
+    """Stratified sample: every nonzero sample is a stored entry (value and subscripts), zero
+    samples are uniform cells with value 0, and the weighted sample loss is an unbiased estimate
+    of the loss over every cell of the tensor (mean over many iterations within 4 standard
+    errors of the dense value)."""
+    rng = np.random.default_rng(3)
+    dims = (6, 5, 4)
+    cells = rng.choice(120, size=25, replace=False)
+    subs = np.stack(np.unravel_index(cells, dims), axis=1).astype(np.int32)
+    vals = rng.random(25) * 3 + 0.5
+    A = [rng.random((I, 2)) * 0.5 for I in dims]
+    dense = np.einsum("ir,jr,kr->ijk", *A)
+    X = np.zeros(dims)
+    X[tuple(subs.T)] = vals
+    full = np.sum(np.exp(dense) - X * dense)          # Poisson loss over every cell
+    est = []
+    counts_nz = np.zeros(25)
+    counts_z = np.zeros(dims)
+    key_rows = {tuple(r): i for i, r in enumerate(subs)}
+    for it in range(400):
+        s, v, w = oracle.gcp_sample(subs, vals, dims, 99, it, 16, 32)
+        for k in range(16):
+            i = key_rows[tuple(s[k])]
+            assert v[k] == vals[i]
+            counts_nz[i] += 1
+        assert np.all(v[16:] == 0.0)
+        np.add.at(counts_z, tuple(s[16:].T), 1)
+        m = dense[tuple(s.T)]
+        est.append(np.sum(w * (np.exp(m) - v * m)))
+    assert np.allclose(w[:16], 25 / 16) and np.allclose(w[16:], (120 - 25) / 32)
+    est = np.array(est)
+    assert abs(est.mean() - full) < 4 * est.std() / np.sqrt(len(est))
+    # uniformity: chi-square statistics far below what a wrong mapping would give
+    e_nz = counts_nz.sum() / 25
+    assert np.sum((counts_nz - e_nz) ** 2 / e_nz) < 25 + 6 * np.sqrt(2 * 25)
+    e_z = counts_z.sum() / 120
+    assert np.sum((counts_z - e_z) ** 2 / e_z) < 120 + 6 * np.sqrt(2 * 120)
+    # deterministic per (seed, iteration); another iteration draws another sample
+    a = oracle.gcp_sample(subs, vals, dims, 99, 7, 16, 32)[0]
+    assert np.array_equal(a, oracle.gcp_sample(subs, vals, dims, 99, 7, 16, 32)[0])
+    assert not np.array_equal(a, oracle.gcp_sample(subs, vals, dims, 99, 8, 16, 32)[0])
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are exactly g and g^2 at every
+    step, so x_t = x_0 - t lr g / (|g| + eps); the lower bound clamps."""
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    x = np.array([1.0, 1.0, 1.0, 1.0])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    lr, eps = 0.01, 1e-8
+    for t in range(1, 31):
+        oracle.adam(x, g, m, v, lr, 0.9, 0.999, eps, t)
+        ref = 1.0 - t * lr * g / (np.abs(g) + eps)
+        assert np.allclose(x, ref, rtol=0, atol=1e-12), t
+    x = np.array([0.005, 1.0])
+    m = np.zeros(2)
+    v = np.zeros(2)
+    oracle.adam(x, np.array([1.0, 1.0]), m, v, 0.01, 0.9, 0.999, 1e-8, 1, lower=0.0)
+    assert x[0] == 0.0 and abs(x[1] - 0.99) < 1e-9
