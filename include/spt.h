@@ -312,6 +312,25 @@ int spt_gcp_fused(const spt_tensor *X, int R, const void *const *factors, int fd
                   int loss_kind, double *loss, void *const *grads, const double *gscale,
                   const spt_tune *tune, void *stream);
 
+/* Stochastic generalized CP (GCP-SGD).  spt_gcp_sample draws iteration `iter`'s stratified
+ * sample on the device with the Philox4x64-10 counter-based generator (Salmon et al., SC'11),
+ * key (seed, 0):
+ *   entries 0..s_nz-1:  stored entry p = floor(r0 * P / 2^64), r = philox((k, iter, 0, 0)); its
+ *                       subscripts and value; weight P / s_nz
+ *   entries s_nz..s_nz+s_z-1 (k = 0..s_z-1): a uniform cell, subscript m = floor(r_m I_m / 2^64),
+ *                       r = philox((k, iter, 1, 0)) (modes 4.. from (k, iter, 1, 1)); value 0;
+ *                       weight (prod I_m - P) / s_z.  Cells holding a stored entry are not
+ *                       rejected (a bias of order P / prod I_m).
+ * subs: device (s_nz + s_z) x d int32; vals, w: device s_nz + s_z values of dtype (SPT_F32 or
+ * SPT_F64).  The sample feeds spt_tensor_create and spt_gcp_forward / spt_gcp_backward with w.
+ * spt_adam_step: one Adam step (Kingma & Ba) on n values of dtype: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, x = max(lower, x - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)),
+ * t >= 1; x, m, v updated in place (device), g read.  Both asynchronous on `stream`. */
+int spt_gcp_sample(const spt_tensor *X, uint64_t seed, int64_t iter, int64_t s_nz, int64_t s_z,
+                   int32_t *subs, void *vals, void *w, int dtype, void *stream);
+int spt_adam_step(void *x, const void *g, void *m, void *v, int64_t n, int dtype, double lr,
+                  double beta1, double beta2, double eps, int64_t t, double lower, void *stream);
+
 /* dst[i] = src[i] * (*g) for n values (dtype SPT_F32 or SPT_F64; src may equal dst; g a device
  * double): the upstream-gradient scaling of a loss computed before its gradient was requested. */
 int spt_scale_values(const void *src, void *dst, int64_t n, int dtype, const double *g,

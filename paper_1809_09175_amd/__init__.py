@@ -400,6 +400,81 @@ class GCPPoissonLoss(torch.autograd.Function):
         return (g[0], g[1], *g[3:])
 
 
+# ------------------------------------------------------------------ stochastic generalized CP
+
+def gcp_sample(X: SparseTensor, seed: int, it: int, s_nz: int, s_z: int, dtype=torch.float32,
+               stream=None):
+    """Iteration `it`'s stratified sample drawn on the device (spt_gcp_sample): subscripts
+    ((s_nz + s_z) x d int32), values and weights (dtype)."""
+    n = int(s_nz) + int(s_z)
+    subs = torch.empty((n, X.d), dtype=torch.int32, device=X.device)
+    vals = torch.empty(n, dtype=dtype, device=X.device)
+    w = torch.empty(n, dtype=dtype, device=X.device)
+    _lib.check(_lib.load().spt_gcp_sample(
+        X.handle, int(seed), int(it), int(s_nz), int(s_z), ctypes.c_void_p(subs.data_ptr()),
+        ctypes.c_void_p(vals.data_ptr()), ctypes.c_void_p(w.data_ptr()), dtype_code(vals),
+        _stream(stream)), "spt_gcp_sample")
+    return subs, vals, w
+
+
+def adam_step(x, g, m, v, t, lr, betas=(0.9, 0.999), eps=1e-8, lower=float("-inf"),
+              stream=None):
+    """One Adam step on CUDA tensors (spt_adam_step); x, m, v updated in place."""
+    for a in (x, g, m, v):
+        _dev_check(a, "adam operand")
+    _lib.check(_lib.load().spt_adam_step(
+        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(g.data_ptr()),
+        ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), x.numel(), dtype_code(x),
+        float(lr), float(betas[0]), float(betas[1]), float(eps), int(t), float(lower),
+        _stream(stream)), "spt_adam_step")
+
+
+def gcp_sgd(X: SparseTensor, factors, loss="poisson", iters=100, samples=(1 << 16, 1 << 16),
+            lr=1e-3, seed=0, lower=None, betas=(0.9, 0.999), eps=1e-8, start=1):
+    """Stochastic generalized CP (GCP-SGD with Adam).  Every iteration draws a stratified sample
+    of s_nz stored entries and s_z uniform cells on the device, evaluates the weighted sample
+    loss and its gradient (spt_gcp_forward / spt_gcp_backward over the sample), and takes an Adam
+    step on every factor.  factors: d CUDA float32/float64 tensors, updated in place.  lower:
+    elementwise lower bound of the factors (default 0 for the Gamma loss, else none).  Returns
+    the sample-loss estimates of every iteration (a CPU float64 tensor)."""
+    lib = _lib.load()
+    fd = dtype_code(factors[0])
+    if fd == SPT_BF16:
+        raise TypeError("GCP-SGD factors must be float32 or float64")
+    kind = _lib.GCP_LOSSES[loss]
+    if lower is None:
+        lower = 0.0 if loss == "gamma" else float("-inf")
+    s_nz, s_z = (int(samples[0]), int(samples[1]))
+    dt = factors[0].dtype
+    R = int(factors[0].shape[1])
+    mom = [torch.zeros_like(f) for f in factors]
+    vel = [torch.zeros_like(f) for f in factors]
+    grads = [torch.empty_like(f) for f in factors]
+    losses = torch.empty(iters, dtype=torch.float64, device=X.device)
+    ws = torch.empty(32768, dtype=torch.uint8, device=X.device)
+    ptrs = _factor_ptrs(factors)
+    gptrs = _lib.ptr_array([g.data_ptr() for g in grads])
+    for k in range(iters):
+        t = start + k
+        subs, vals, w = gcp_sample(X, seed, t, s_nz, s_z, dtype=dt)
+        S = SparseTensor(subs, vals, X.dims)
+        m = torch.empty(s_nz + s_z, dtype=dt, device=X.device)
+        y = torch.empty_like(m)
+        _lib.check(lib.spt_gcp_forward(S.handle, R, ptrs, fd, kind, ctypes.c_void_p(w.data_ptr()),
+                                       ctypes.c_void_p(m.data_ptr()),
+                                       ctypes.c_void_p(losses[k:].data_ptr()),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()),
+                   "spt_gcp_forward")
+        _lib.check(lib.spt_gcp_backward(S.handle, R, ptrs, fd, kind, ctypes.c_void_p(w.data_ptr()),
+                                        ctypes.c_void_p(m.data_ptr()), None,
+                                        ctypes.c_void_p(y.data_ptr()), gptrs, None, _stream()),
+                   "spt_gcp_backward")
+        for f, g, a, b in zip(factors, grads, mom, vel):
+            adam_step(f, g, a, b, t, lr, betas, eps, lower)
+        S.close()
+    return losses.cpu()
+
+
 # ------------------------------------------------------------------ autotuner and batching
 
 def autotune(X: SparseTensor, factors, mode: int, batch=False, algos=("atomic", "permuted"),

@@ -77,6 +77,11 @@ SIGNATURES = {
                                 _c_p, _c_p]),
     "spt_gcp_fused": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "spt_scale_values": (_c_i, [_c_p, _c_p, _c_i64, _c_i, _c_p, _c_p]),
+    "spt_gcp_sample": (_c_i, [_c_p, ctypes.c_uint64, _c_i64, _c_i64, _c_i64, _c_p, _c_p, _c_p,
+                              _c_i, _c_p]),
+    "spt_adam_step": (_c_i, [_c_p, _c_p, _c_p, _c_p, _c_i64, _c_i, ctypes.c_double,
+                             ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_i64,
+                             ctypes.c_double, _c_p]),
     "spt_f32_to_bf16": (_c_i, [_c_p, _c_p, _c_i64, _c_p]),
     "spt_stream_triad": (_c_i, [_c_p, _c_p, _c_p, ctypes.c_float, _c_i64, _c_p]),
 }
