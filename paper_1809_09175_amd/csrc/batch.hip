@@ -142,10 +142,9 @@ static int batch_cfg_index(int algo, int d, int G, int CPL) {
     return -1;
 }
 
-static size_t batch_smem_for(int cfg, int R, int *hbits) {
+static size_t batch_smem_for(int cfg, int *hbits) {
     const BatchCfg &c = kBatchCfgs[cfg];
     const int rq = 1;  // 3-way FP32 records are 16 bytes
-    (void)R;
     if (c.algo == SPT_ALGO_PERMUTED) {
         *hbits = 0;
         return (size_t)(kBlock / kWave) * perm_shared_bytes(c.G, c.CPL, rq, 4);
@@ -212,7 +211,7 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         b.cfg = cfg;
         b.chunk = t.nnz_per_wave;
         int hb = 0;
-        const size_t sm = batch_smem_for(cfg, R, &hb);
+        const size_t sm = batch_smem_for(cfg, &hb);
         b.hbits = hb;
         smem = sm > smem ? sm : smem;
         units += ceil_div(X->P, (int64_t)(kBlock / kWave) * t.nnz_per_wave);
