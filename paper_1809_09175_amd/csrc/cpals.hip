@@ -534,7 +534,15 @@ __global__ __launch_bounds__(kBlock) void k_loss_final(const double *__restrict_
 // lane layout of the model-value pass: 8 lanes per entry with up to 8 columns each (wide
 // loads, a 3-step group reduction), else one column per lane
 static void model_layout(int R, int *G, int *CPL) {
-    const int opts[] = {1, 2, 4, 8};  // fewest columns per lane that cover R with 8 lanes
+    // four lanes per entry at R = 16 and 32 (4 x 4, 4 x 8 columns; fewer butterfly steps per entry:
+    // fit at R = 32 on the 1e8-entry power-law tensor 1.73 ms against 2.39 ms with 8 x 4),
+    // else the fewest columns per lane that cover R with 8 lanes
+    if (R == 16 || R == 32) {
+        *G = 4;
+        *CPL = R / 4;
+        return;
+    }
+    const int opts[] = {1, 2, 4, 8};
     for (int c : opts)
         if (R % c == 0 && R / c <= 8) {
             *G = 8;
@@ -566,6 +574,8 @@ static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
                            loss);                                                              \
         break;
     switch (G * 16 + CPL) {
+        SPT_MODEL_CFG(4, 4)
+        SPT_MODEL_CFG(4, 8)
         SPT_MODEL_CFG(8, 1)
         SPT_MODEL_CFG(8, 2)
         SPT_MODEL_CFG(8, 4)
