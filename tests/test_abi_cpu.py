@@ -56,6 +56,17 @@ def test_host_argument_checks(lib):
     assert lib.spt_cp_workspace_bytes(None, 8) == 0
     assert lib.spt_f32_to_bf16(None, None, -1, None) == -1
     assert lib.spt_stream_triad(None, None, None, ctypes.c_float(1.0), -5, None) == -1
+    # generalized-CP entry points: null tensor / loss, bad loss kind, bad sizes and steps
+    assert lib.spt_gcp_fused(None, 8, None, 1, 0, None, None, None, None, None) == -1
+    assert lib.spt_gcp_forward(None, 8, None, 1, 4, None, None, None, None, 0, None) == -1
+    assert lib.spt_gcp_sample(None, 1, 0, 4, 4, None, None, None, 1, None) == -1
+    assert lib.spt_adam_step(None, None, None, None, 10, 1, 1e-3, 0.9, 0.999, 1e-8, 0,
+                             float("-inf"), None) == -1                   # step t = 0
+    assert lib.spt_adam_step(None, None, None, None, 0, 2, 1e-3, 0.9, 0.999, 1e-8, 1,
+                             float("-inf"), None) == -1                   # BF16 not supported
+    assert lib.spt_adam_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, 1,
+                             float("-inf"), None) == 0                    # empty: nothing to do
+    assert lib.spt_scale_values(None, None, 5, 1, None, None) == -1
 
 
 def test_workspace_accounting_matches_section5_storage():
