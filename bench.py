@@ -189,6 +189,40 @@ def bench_batch64(spt, datagen, torch, dev, reps=10):
     return res
 
 
+def bench_shard_share(spt, torch, T, X, dev, R, shards=8):
+    """The kernel at one GPU's share of a row-owning split over `shards` GPUs: for each mode n,
+    the first 1/shards of the entries in mode-n order (a contiguous range of output rows) as a
+    tensor of its own, with the full factor matrices; MTTKRP time of that mode on it."""
+    out = []
+    subs_all = None
+    for n in range(X.d):
+        perm, _ = T.perm(n)
+        q = perm[: X.nnz // shards].long()
+        if subs_all is None:
+            subs_all = torch.from_numpy(X.subs).to(dev)
+            vals_all = torch.from_numpy(X.vals).to(dev)
+        S = spt.SparseTensor(subs_all[q].contiguous(), vals_all[q].contiguous(), X.dims)
+        S.permute(n)
+        S.sort_copy(n)
+        A = [torch.rand(I, R, device=dev) for I in X.dims]
+        V = torch.empty(X.dims[n], R, device=dev)
+        spt.mttkrp(S, A, n, out=V)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            spt.mttkrp(S, A, n, out=V)
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(round(e0.elapsed_time(e1) / 10, 3))
+        S.close()
+        del S, q
+    del subs_all, vals_all
+    torch.cuda.empty_cache()
+    return {"entries_per_shard": X.nnz // shards, "rank": R, "mttkrp_ms_per_mode": out}
+
+
 def bench_gcp(spt, datagen, torch, dev, R=32, steps=3):
     """Generalized CP (Poisson log link) forward + backward on the count tensor: 5e7 nonzeros
     plus 5e7 sampled zeros; the backward is one MTTKRP per mode of the derivative tensor."""
@@ -405,6 +439,7 @@ def main():
         lib = spt._lib.load()
         extras["sorted_copy_bytes_all_modes"] = int(lib.spt_tensor_sorted_copy_bytes(T.handle, -1))
         extras["tensor_workspace_bytes"] = int(T.ws.numel())
+        extras["one_gpu_share_of_8"] = bench_shard_share(spt, torch, T, X, dev, R, shards=8)
         extras["sort_over_cp_als_iteration"] = round(sort_ms / (sweep_ms + fit_ms), 3)
         extras["sort_and_copy_over_cp_als_iteration"] = round((sort_ms + copy_ms) / (sweep_ms + fit_ms), 3)
         log(f"CP-ALS sweep {sweep_ms:.2f} ms, fit {fit_ms:.2f} ms")
