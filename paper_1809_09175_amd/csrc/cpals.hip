@@ -145,11 +145,12 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__
 
 // ------------------------------------------------------------------------------------------
 // Hadamard product of the other modes' Grams (the whole workgroup) and its Cholesky factor (the
-// first wavefront alone: lane r owns row r, so the column steps synchronise with wave barriers
-// instead of workgroup barriers).  Same
-// column-by-column order as the textbook algorithm; no FMA contraction here so the factor
-// follows the plain definition's rounding.
-// ------------------------------------------------------------------------------------------
+// first wavefront alone).  Lane r owns row r of L in registers; row c of L, which lane c wrote
+// to LDS as it computed it, is read into registers with independent LDS broadcasts at the start
+// of column step c, so each step is one dependent chain of register arithmetic; the steps
+// synchronise with wave barriers.  Same column-by-column order and operation order as the textbook algorithm, and no
+// FMA contraction, so the factor follows the plain definition's rounding.
+template <int RMAX>
 __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restrict__ grams, int d,
                                                           int n, int R, double *__restrict__ L,
                                                           SptStatusBlock *st) {
@@ -160,22 +161,34 @@ __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restri
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
+    for (int e = tid; e < kCpMaxR * kCpMaxR; e += kBlock) Lc[e / kCpMaxR][e % kCpMaxR] = 0.0;
     for (int ab = tid; ab < R * R; ab += kBlock) {
         double g = 1.0;
         for (int m = 0; m < d; ++m)
             if (m != n) g *= grams[(int64_t)m * R * R + ab];
         S[ab / R][ab % R] = g;
-        Lc[ab / R][ab % R] = 0.0;
     }
     __syncthreads();
     if (tid >= kWave) return;
+    const int r = tid;
     double maxdiag = 0.0;
     for (int k = 0; k < R; ++k) maxdiag = S[k][k] > maxdiag ? S[k][k] : maxdiag;
     const double tol = (double)R * 2.220446049250313e-16 * maxdiag;
+    // Column step c: every lane forms s = S[r][c] - sum_k L[r][k] L[c][k] over all RMAX columns;
+    // the terms from column c on are 0 * 0 (neither row has them yet) and leave s unchanged, so
+    // the sums equal the textbook ones term for term.  Lane c's s is the pivot.
+    double row[RMAX];
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k) row[k] = 0.0;
     for (int c = 0; c < R; ++c) {
-        if (tid == 0) {
-            double piv = S[c][c];
-            for (int k = 0; k < c; ++k) piv -= Lc[c][k] * Lc[c][k];
+        double lrow[RMAX];
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) lrow[k] = Lc[c][k];  // row c of L so far (LDS broadcast)
+        double sacc = S[r][c];
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k) sacc -= row[k] * lrow[k];
+        if (r == c) {
+            double piv = sacc;
             if (!(piv > tol)) {
                 bad = 1;
                 piv = 1.0;  // keep the factor finite; the status word reports the failure
@@ -185,11 +198,15 @@ __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restri
         }
         wave_sync();
         const double lcc = lcc_s;
-        for (int r = c + 1 + tid; r < R; r += kWave) {
-            double s = S[r][c];
-            for (int k = 0; k < c; ++k) s -= Lc[r][k] * Lc[c][k];
-            Lc[r][c] = s / lcc;
+        double v = 0.0;
+        if (r == c) v = lcc;
+        if (r > c && r < R) {
+            v = sacc / lcc;
+            Lc[r][c] = v;
         }
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+            if (k == c) row[k] = v;
         wave_sync();
     }
     for (int ab = tid; ab < R * R; ab += kWave) L[ab] = Lc[ab / R][ab % R];
@@ -725,8 +742,15 @@ int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fd
     // V = MTTKRP with the other (normalised) factors and unit weights
     rc = launch_mttkrp(X, mode, R, (const void *const *)factors, fdtype, nullptr, nullptr, V, t, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_hadamard_chol, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R, Lf,
-                       X->status);
+    if (R <= 16)
+        hipLaunchKernelGGL(k_hadamard_chol<16>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
+                           Lf, X->status);
+    else if (R <= 32)
+        hipLaunchKernelGGL(k_hadamard_chol<32>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
+                           Lf, X->status);
+    else
+        hipLaunchKernelGGL(k_hadamard_chol<64>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
+                           Lf, X->status);
     SPT_LAUNCH_CHECK();
     rc = (fdtype == SPT_F64) ? launch_solve<double>((const double *)V, I, R, Lf, Y, s)
                              : launch_solve<float>((const float *)V, I, R, Lf, Y, s);

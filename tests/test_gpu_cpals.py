@@ -113,6 +113,34 @@ def test_cp_mode_update_low_precision(gpu, kind):
         assert _relerr(st.grams[n].cpu().numpy(), stored.T @ stored) < 1e-12
 
 
+@pytest.mark.parametrize("R", [5, 20, 40, 64])
+def test_cp_mode_update_fp64_ranks(gpu, R):
+    """FP64 mode updates at ranks off the 16/32/64 grid (padded Cholesky, solve and Gram tiles)
+    and at the largest rank, against the oracle's mode update from the same state."""
+    import paper_1809_09175_amd as spt
+    X = _skewed4_small()
+    X.vals = X.vals.astype(np.float64)
+    T = _dev_tensor(X, np.float64)
+    T.permute()
+    A = datagen.factors(X.dims, R, seed=R, dtype=np.float64)
+    st = spt.CPState(T, [torch.from_numpy(a.copy()).cuda() for a in A])
+    for n in range(4):
+        Ain = [_np(f) for f in st.factors]
+        lin = st.lam.cpu().numpy()
+        Gin = st.grams.cpu().numpy()
+        _log(f"fp64 mode update R={R} n={n}")
+        st.mode_update(n)
+        Ao, lo, Go = oracle.cp_als_mode(X.subs, X.vals, X.dims, Ain, lin, Gin, n)
+        Gam = np.ones((R, R))
+        for m in range(4):
+            if m != n:
+                Gam *= Gin[m]
+        tol = 1e-13 * max(1.0, np.linalg.cond(Gam))
+        assert _relerr(_np(st.factors[n]), Ao[n]) < tol, (n, np.linalg.cond(Gam))
+        assert _relerr(st.lam.cpu().numpy(), lo) < tol
+        assert _relerr(st.grams[n].cpu().numpy(), Go[n]) < 1e-12
+
+
 @pytest.mark.parametrize("copy_mode", [None, 0, 2])
 def test_fit_matches_oracle_fp32_factors(gpu, copy_mode):
     """Fit from FP32 factors: over the records in storage order, and over a sorted record copy
