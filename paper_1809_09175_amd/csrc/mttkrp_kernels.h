@@ -214,20 +214,26 @@ __device__ __forceinline__ T gcp_dloss(int loss, T x, T m) {
 // m = sum_j prod_m A^(m)(l_m, j) (product in mode order, this lane's columns summed, then a
 // butterfly over the G lanes of the group), y = df(x, m), and the gradient row contribution
 // t = y * prod_{m != n} A^(m)(l_m, j).  lterm receives f(x, m).  All lanes of the group must
-// take part (the butterfly); lanes past column R add nothing to m.
+// take part (the butterfly); lanes past column R add nothing to m.  The mode-n row is kept in
+// an[] across calls and loaded only when the key differs from ankey (the caller starts ankey at
+// -1): along the sorted order a lane group meets each mode-n row in one run, so the row is
+// fetched once per run instead of once per entry.
 template <int D, int RW, int G, int CPL, class FT, class AT>
 __device__ __forceinline__ void entry_gcp(const int *w, int key, const OtherModes<D> &om,
                                           const char *anb, int n, uint32_t rowbytes,
                                           uint32_t colbytes, bool colok, int loss, AT *t,
-                                          double &lterm) {
-    AT f[D - 1][CPL], an[CPL];
+                                          double &lterm, AT *an, int &ankey) {
+    AT f[D - 1][CPL];
 #pragma unroll
     for (int j = 0; j < D - 1; ++j) {
         const int sub = (w[j] & ~om.up[j]) | (w[j + 1] & om.up[j]);
         load_cols<FT, CPL, AT>(reinterpret_cast<const FT *>(om.base[j] + (uint32_t)sub * rowbytes + colbytes),
                                f[j]);
     }
-    load_cols<FT, CPL, AT>(reinterpret_cast<const FT *>(anb + (uint32_t)key * rowbytes + colbytes), an);
+    if (key != ankey) {
+        load_cols<FT, CPL, AT>(reinterpret_cast<const FT *>(anb + (uint32_t)key * rowbytes + colbytes), an);
+        ankey = key;
+    }
     const AT x = rec_value<AT, RW>(w);
     AT q = 0;
 #pragma unroll
@@ -361,7 +367,11 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
     const OtherModes<D> om = other_modes<D>(A, n);
     const char *anb = reinterpret_cast<const char *>(A.p[n]);
     double lacc = 0.0;
+    AT an[CPL];
+    int ankey = -1;
     (void)anb;
+    (void)an;
+    (void)ankey;
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
     const int S = chunk / NG;  // slice per group
     const int64_t gb = c0 + (int64_t)g * S;
@@ -444,7 +454,7 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                     if constexpr (GCP) {
                         double lt;
                         entry_gcp<D, RW, G, CPL, FT, AT>(w, kk[u], om, anb, n, rowbytes, colbytes,
-                                                         colok, loss_kind, t[u], lt);
+                                                         colok, loss_kind, t[u], lt, an, ankey);
                         lacc += (gl == 0) ? lt : 0.0;
                     } else {
                         entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
@@ -461,7 +471,7 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
                         if constexpr (GCP) {
                             double lt;
                             entry_gcp<D, RW, G, CPL, FT, AT>(w, kk[u], om, anb, n, rowbytes,
-                                                             colbytes, colok, loss_kind, t[u], lt);
+                                                             colbytes, colok, loss_kind, t[u], lt, an, ankey);
                             lacc += (gl == 0) ? lt : 0.0;
                         } else {
                             entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
