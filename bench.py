@@ -437,7 +437,7 @@ def main():
         extras["ingest_pack_validate_ms"] = round(pack_ms, 1)
         # memory side of the trade: one record array per mode beside the records themselves
         lib = spt._lib.load()
-        extras["sorted_copy_bytes_all_modes"] = int(lib.spt_tensor_sorted_copy_bytes(T.handle, -1))
+        extras["sorted_copy_bytes_all_modes"] = int(lib.spt_tensor_sorted_copy_bytes(T.handle, -1, 1))
         extras["tensor_workspace_bytes"] = int(T.ws.numel())
         extras["one_gpu_share_of_8"] = bench_shard_share(spt, torch, T, X, dev, R, shards=8)
         extras["sort_over_cp_als_iteration"] = round(sort_ms / (sweep_ms + fit_ms), 3)

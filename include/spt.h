@@ -57,7 +57,8 @@ typedef enum spt_algo {
                               wave segmented reduction */
     SPT_ALGO_PERMUTED_COPY = 3, /* the same traversal reading a mode-sorted copy of the records
                                    (spt_tensor_sort_copy): records stream instead of being
-                                   gathered; results identical to SPT_ALGO_PERMUTED */
+                                   gathered; with a storage-ordered copy the rows are summed in
+                                   the order SPT_ALGO_PERMUTED sums them */
     SPT_ALGO_PRIVATIZED = 4 /* storage-order traversal into a per-workgroup LDS copy of the whole
                                output, flushed once per workgroup: the hybrid of atomics and
                                private copies that Sec. 7 proposes for short modes; only when
@@ -136,14 +137,29 @@ int spt_tensor_permute(spt_tensor *X, int mode, void *stream);
 int spt_tensor_perm(const spt_tensor *X, int mode, const int32_t **perm, const int32_t **skey);
 
 /* Mode-sorted copies of the packed records (a memory-for-bandwidth trade the paper avoided for
- * 12-16 GB GPUs, Sec. 5): the copy of mode n holds record perm_n[q] at position q, so the
- * permuted MTTKRP streams records instead of gathering them.  Needs spt_tensor_permute(mode)
- * first (SPT_ESTATE otherwise); mode = -1 copies every mode back to back.  ws: device buffer of
- * at least spt_tensor_sorted_copy_bytes(X, mode) bytes, 256-byte aligned, caller-owned, kept
- * alive until the copy is dropped or the handle destroyed.  A later spt_tensor_permute of a mode
- * drops its copy.  With a copy present, SPT_ALGO_AUTO selects SPT_ALGO_PERMUTED_COPY. */
-size_t spt_tensor_sorted_copy_bytes(const spt_tensor *X, int mode);
-int spt_tensor_sort_copy(spt_tensor *X, int mode, void *ws, size_t ws_bytes, void *stream);
+ * 12-16 GB GPUs, Sec. 5), so the permuted MTTKRP streams records instead of gathering them.
+ * The copy of mode n holds the records grouped by their mode-n subscript in increasing order;
+ * within a group, order selects:
+ *   SPT_COPY_STORAGE_ORDER   storage order: position q holds record perm_n[q];
+ *   SPT_COPY_BY_SECOND_MODE  increasing subscript of a second mode m, then storage order, where
+ *                            m is the other mode with the most rows (lowest index among equals):
+ *                            consecutive entries of a row then share or neighbour their mode-m
+ *                            factor rows, which raises the cache hit rate of the gathers.  Needs
+ *                            mode m permuted as well; the copy carries its own order array
+ *                            (4 bytes per entry), used where replacement values are read.
+ * Needs spt_tensor_permute(mode) first (SPT_ESTATE otherwise); mode = -1 copies every mode back
+ * to back.  ws: device buffer of at least spt_tensor_sorted_copy_bytes(X, mode, order) bytes,
+ * 256-byte aligned, caller-owned, kept alive until the copy is dropped or the handle destroyed;
+ * the second-mode order also uses the tensor's sort scratch.  A later spt_tensor_permute of a
+ * mode drops its copy.  With a copy present, SPT_ALGO_AUTO selects SPT_ALGO_PERMUTED_COPY.
+ * SPT_EINVAL for an unknown order (and 0 bytes from the size query). */
+typedef enum spt_copy_order {
+    SPT_COPY_STORAGE_ORDER = 0,
+    SPT_COPY_BY_SECOND_MODE = 1
+} spt_copy_order;
+size_t spt_tensor_sorted_copy_bytes(const spt_tensor *X, int mode, int order);
+int spt_tensor_sort_copy(spt_tensor *X, int mode, int order, void *ws, size_t ws_bytes,
+                         void *stream);
 int spt_tensor_drop_sorted_copy(spt_tensor *X, int mode);
 
 int spt_tensor_info(const spt_tensor *X, int *d, int64_t *dims, int64_t *nnz, int *vals_dtype);

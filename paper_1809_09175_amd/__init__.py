@@ -19,6 +19,8 @@ __all__ = ["SparseTensor", "mttkrp", "CPState", "cp_als", "model_values", "GCPLo
            "SptUnavailable",
            "ALGO_AUTO", "ALGO_ATOMIC", "ALGO_PERMUTED", "dtype_code"]
 
+COPY_ORDERS = {"storage": 0, "second_mode": 1}
+
 _ALGOS = {"auto": ALGO_AUTO, "atomic": ALGO_ATOMIC, "permuted": ALGO_PERMUTED,
           "permuted_copy": ALGO_PERMUTED_COPY, "privatized": ALGO_PRIVATIZED,
           ALGO_AUTO: ALGO_AUTO, ALGO_ATOMIC: ALGO_ATOMIC, ALGO_PERMUTED: ALGO_PERMUTED,
@@ -100,15 +102,26 @@ class SparseTensor:
                    "spt_tensor_permute")
         return self
 
-    def sort_copy(self, mode: int = -1, stream=None):
+    def sort_copy(self, mode: int = -1, order: str = "auto", stream=None):
         """Build mode-sorted copies of the records (needs permute(mode) first); the permuted
-        MTTKRP then streams records instead of gathering them.  Costs one record array
-        (16 or 32 bytes per entry) per mode."""
+        MTTKRP then streams records instead of gathering them.  Within a row the entries follow
+        `order`: "second_mode" (increasing subscript of the other mode with the most rows, which
+        must be permuted too; better cache reuse of the gathered factor rows), "storage", or
+        "auto" (second_mode where that mode is permuted, else storage).  Costs one record array
+        (16 or 32 bytes per entry) per mode, plus 4 bytes per entry for the second-mode order."""
         lib = _lib.load()
-        nbytes = lib.spt_tensor_sorted_copy_bytes(self._h, int(mode))
-        buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        _lib.check(lib.spt_tensor_sort_copy(self._h, int(mode), ctypes.c_void_p(buf.data_ptr()),
-                                            nbytes, _stream(stream)), "spt_tensor_sort_copy")
+        orders = ("second_mode", "storage") if order == "auto" else (order,)
+        for k, name in enumerate(orders):
+            o = COPY_ORDERS[name]
+            nbytes = lib.spt_tensor_sorted_copy_bytes(self._h, int(mode), o)
+            buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            rc = lib.spt_tensor_sort_copy(self._h, int(mode), o, ctypes.c_void_p(buf.data_ptr()),
+                                          nbytes, _stream(stream))
+            # the state check precedes any launch, so "auto" can retry in storage order
+            if rc == -7 and k + 1 < len(orders):
+                continue
+            _lib.check(rc, "spt_tensor_sort_copy")
+            break
         if not hasattr(self, "_copies"):
             self._copies = {}
         self._copies[int(mode)] = buf

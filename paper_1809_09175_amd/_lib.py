@@ -44,8 +44,8 @@ SIGNATURES = {
     "spt_tensor_status": (_c_i, [_c_p, _c_p]),
     "spt_tensor_permute": (_c_i, [_c_p, _c_i, _c_p]),
     "spt_tensor_perm": (_c_i, [_c_p, _c_i, _c_p, _c_p]),
-    "spt_tensor_sorted_copy_bytes": (_c_sz, [_c_p, _c_i]),
-    "spt_tensor_sort_copy": (_c_i, [_c_p, _c_i, _c_p, _c_sz, _c_p]),
+    "spt_tensor_sorted_copy_bytes": (_c_sz, [_c_p, _c_i, _c_i]),
+    "spt_tensor_sort_copy": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_sz, _c_p]),
     "spt_tensor_drop_sorted_copy": (_c_i, [_c_p, _c_i]),
     "spt_tensor_info": (_c_i, [_c_p, _c_p, _c_p, _c_p, _c_p]),
     "spt_tensor_destroy": (_c_i, [_c_p]),

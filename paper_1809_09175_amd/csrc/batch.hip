@@ -199,8 +199,8 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         BatchItem &b = h[i];
         memset(&b, 0, sizeof b);
         b.rec = X->rec;
-        b.perm = X->perm[n];
         b.srec = (t.algo == SPT_ALGO_PERMUTED_COPY) ? X->srec[n] : nullptr;
+        b.perm = (b.srec != nullptr) ? X->sperm[n] : X->perm[n];
         for (int m = 0; m < X->d; ++m) b.A[m] = factors[i][m];
         b.V = outputs[i];
         b.P = X->P;

@@ -177,8 +177,8 @@ int spt_gcp_fused(const spt_tensor *X, int R, const void *const *factors, int fd
         }
         FusedArgs a;
         a.rec = X->rec;
-        a.perm = X->perm[n];
         a.srec = (t.algo == SPT_ALGO_PERMUTED_COPY) ? X->srec[n] : nullptr;
+        a.perm = (a.srec != nullptr) ? X->sperm[n] : X->perm[n];
         a.P = X->P;
         a.n = n;
         a.R = R;

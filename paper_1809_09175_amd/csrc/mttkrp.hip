@@ -164,8 +164,8 @@ int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *facto
     if (X->P == 0) return SPT_OK;
     MttkrpArgs a;
     a.rec = X->rec;
-    a.perm = X->perm[mode];
     a.srec = (t.algo == SPT_ALGO_PERMUTED_COPY) ? X->srec[mode] : nullptr;
+    a.perm = (a.srec != nullptr) ? X->sperm[mode] : X->perm[mode];
     a.P = X->P;
     a.n = mode;
     a.R = R;

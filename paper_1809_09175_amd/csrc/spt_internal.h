@@ -28,6 +28,7 @@ struct spt_tensor {
     int32_t *perm[SPT_MAX_ORDER];
     int32_t *skey[SPT_MAX_ORDER];
     int4 *srec[SPT_MAX_ORDER];  // optional mode-sorted record copies (caller workspace)
+    const int32_t *sperm[SPT_MAX_ORDER];  // storage position of each record of srec[n]
     int32_t *tmp_keys;   // radix-sort ping-pong buffers
     int32_t *tmp_vals;
     uint32_t *hist;      // 256 x ntiles digit counts, scanned in place

@@ -293,6 +293,7 @@ static int bit_width(int64_t x) {  // bits needed for values 0..x
 static int permute_mode(spt_tensor *X, int n, hipStream_t s) {
     const int64_t P = X->P;
     X->srec[n] = nullptr;
+    X->sperm[n] = nullptr;
     if (P == 0) {
         X->permuted[n] = 1;
         return SPT_OK;
@@ -519,37 +520,129 @@ int spt_tensor_permute(spt_tensor *X, int mode, void *stream) {
     return SPT_OK;
 }
 
-size_t spt_tensor_sorted_copy_bytes(const spt_tensor *X, int mode) {
+// keys[i] = mode-n subscript of entry idx[i]
+__global__ __launch_bounds__(kBlock) void k_gather_keys(const int32_t *__restrict__ recw, int rw,
+                                                        int n, const int32_t *__restrict__ idx,
+                                                        int64_t P, int32_t *__restrict__ keys) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P; i += stride)
+        keys[i] = recw[(int64_t)idx[i] * rw + n];
+}
+
+// The other mode with the most rows (lowest index among equals): the one whose factor rows a
+// mode-n traversal is least likely to find in cache.
+static int second_mode(const spt_tensor *X, int n) {
+    int m2 = -1;
+    for (int m = 0; m < X->d; ++m)
+        if (m != n && (m2 < 0 || X->dims[m] > X->dims[m2])) m2 = m;
+    return m2;
+}
+
+static size_t copy_bytes_one(const spt_tensor *X, int order) {
+    const size_t recs = align256((size_t)X->P * X->rec_words * 4);
+    return order == SPT_COPY_BY_SECOND_MODE ? recs + align256((size_t)X->P * 4) : recs;
+}
+
+size_t spt_tensor_sorted_copy_bytes(const spt_tensor *X, int mode, int order) {
     if (X == nullptr || mode < -1 || mode >= X->d) return 0;
-    const size_t one = align256((size_t)X->P * X->rec_words * 4);
+    if (order != SPT_COPY_STORAGE_ORDER && order != SPT_COPY_BY_SECOND_MODE) return 0;
+    const size_t one = copy_bytes_one(X, order);
     return mode == -1 ? one * X->d : one;
 }
 
-int spt_tensor_sort_copy(spt_tensor *X, int mode, void *ws, size_t ws_bytes, void *stream) {
+// Order of the entries by (mode-n subscript, mode-m subscript, storage position): perm_m, which
+// is stable in mode m, stably re-sorted by the mode-n subscript with the LSD passes of
+// permute_mode.  scratch holds three arrays of P int32 (gathered keys and one ping-pong pair);
+// the other pair is tmp_keys / q, so the last pass leaves the order in q.
+static int order_by_two_modes(spt_tensor *X, int n, int m, int32_t *scratch, int32_t *q,
+                              hipStream_t s) {
+    const int64_t P = X->P;
+    const int64_t words = (P + 3) & ~(int64_t)3;
+    int32_t *k0 = scratch, *k1 = scratch + words, *v1 = scratch + 2 * words;
+    const int nbits = bit_width(X->dims[n] - 1);
+    if (nbits == 0) {
+        if (hipMemcpyAsync(q, X->perm[m], (size_t)P * 4, hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+            return SPT_EHIP;
+        return SPT_OK;
+    }
+    const int32_t *recw = reinterpret_cast<const int32_t *>(X->rec);
+    int64_t gblocks = ceil_div(P, kBlock);
+    if (gblocks > 65536) gblocks = 65536;
+    hipLaunchKernelGGL(k_gather_keys, dim3((unsigned)gblocks), dim3(kBlock), 0, s, recw,
+                       X->rec_words, n, X->perm[m], P, k0);
+    SPT_LAUNCH_CHECK();
+    const int passes = (nbits + 7) / 8;
+    const int64_t ntiles = ceil_div(P, kSortTile);
+    const int64_t L = 256 * ntiles;
+    const int64_t nseg = ceil_div(L, kScanSeg);
+    const int32_t *ik = k0, *iv = X->perm[m];
+    for (int pass = 0; pass < passes; ++pass) {
+        const bool to_final = ((passes - 1 - pass) % 2) == 0;
+        int32_t *ok = to_final ? X->tmp_keys : k1;
+        int32_t *ov = to_final ? q : v1;
+        const int shift = pass * 8;
+        dim3 g((unsigned)ntiles), b(kBlock);
+        hipLaunchKernelGGL(k_radix_hist<false>, g, b, 0, s, ik, recw, X->rec_words, n, P, shift,
+                           X->hist, ntiles);
+        SPT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nseg), b, 0, s, X->hist, L,
+                           X->scan_part);
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), b, 0, s, X->scan_part, nseg);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nseg), b, 0, s, X->hist, L, X->scan_part);
+        SPT_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_radix_scatter<false>, g, b, 0, s, ik, iv, recw, X->rec_words, n, P,
+                           shift, X->hist, ntiles, ok, ov);
+        SPT_LAUNCH_CHECK();
+        ik = ok;
+        iv = ov;
+    }
+    return SPT_OK;
+}
+
+int spt_tensor_sort_copy(spt_tensor *X, int mode, int order, void *ws, size_t ws_bytes,
+                         void *stream) {
     if (X == nullptr || mode < -1 || mode >= X->d) return SPT_EINVAL;
-    const size_t need = spt_tensor_sorted_copy_bytes(X, mode);
+    if (order != SPT_COPY_STORAGE_ORDER && order != SPT_COPY_BY_SECOND_MODE) return SPT_EINVAL;
+    const size_t need = spt_tensor_sorted_copy_bytes(X, mode, order);
     if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < need) return SPT_EWORKSPACE;
-    for (int n = 0; n < X->d; ++n)
-        if ((mode == -1 || n == mode) && !X->permuted[n]) return SPT_ESTATE;
+    for (int n = 0; n < X->d; ++n) {
+        if (mode != -1 && n != mode) continue;
+        if (!X->permuted[n]) return SPT_ESTATE;
+        if (order == SPT_COPY_BY_SECOND_MODE && !X->permuted[second_mode(X, n)])
+            return SPT_ESTATE;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint8_t *w = static_cast<uint8_t *>(ws);
-    const size_t one = align256((size_t)X->P * X->rec_words * 4);
+    const size_t recs = align256((size_t)X->P * X->rec_words * 4);
     for (int n = 0; n < X->d; ++n) {
         if (mode != -1 && n != mode) continue;
         int4 *dst = reinterpret_cast<int4 *>(w);
-        w += one;
+        const int32_t *q = X->perm[n];
+        if (order == SPT_COPY_BY_SECOND_MODE) {
+            int32_t *qd = reinterpret_cast<int32_t *>(w + recs);
+            if (X->P > 0) {
+                // the record area is free until the records are gathered into it
+                int rc = order_by_two_modes(X, n, second_mode(X, n), reinterpret_cast<int32_t *>(w),
+                                            qd, s);
+                if (rc) return rc;
+            }
+            q = qd;
+        }
+        w += copy_bytes_one(X, order);
         if (X->P > 0) {
             int64_t blocks = ceil_div(X->P, kBlock);
             if (blocks > 65536) blocks = 65536;
             if (X->rec_words == 4)
                 hipLaunchKernelGGL(k_gather_records<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                                   X->rec, X->perm[n], X->P, dst);
+                                   X->rec, q, X->P, dst);
             else
                 hipLaunchKernelGGL(k_gather_records<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                                   X->rec, X->perm[n], X->P, dst);
+                                   X->rec, q, X->P, dst);
             SPT_LAUNCH_CHECK();
         }
         X->srec[n] = dst;
+        X->sperm[n] = q;
     }
     return SPT_OK;
 }
@@ -557,7 +650,10 @@ int spt_tensor_sort_copy(spt_tensor *X, int mode, void *ws, size_t ws_bytes, voi
 int spt_tensor_drop_sorted_copy(spt_tensor *X, int mode) {
     if (X == nullptr || mode < -1 || mode >= X->d) return SPT_EINVAL;
     for (int n = 0; n < X->d; ++n)
-        if (mode == -1 || n == mode) X->srec[n] = nullptr;
+        if (mode == -1 || n == mode) {
+            X->srec[n] = nullptr;
+            X->sperm[n] = nullptr;
+        }
     return SPT_OK;
 }
 

@@ -67,6 +67,10 @@ def test_host_argument_checks(lib):
     assert lib.spt_adam_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, 1,
                              float("-inf"), None) == 0                    # empty: nothing to do
     assert lib.spt_scale_values(None, None, 5, 1, None, None) == -1
+    # sorted copies: null tensor for either order; the size query answers 0
+    assert lib.spt_tensor_sorted_copy_bytes(None, -1, 0) == 0
+    assert lib.spt_tensor_sorted_copy_bytes(None, 0, 1) == 0
+    assert lib.spt_tensor_sort_copy(None, -1, 1, None, 0, None) == -1
 
 
 def test_workspace_accounting_matches_section5_storage():

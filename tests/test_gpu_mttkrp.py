@@ -270,35 +270,97 @@ def test_powerlaw3_full_size_sampled(gpu):
 
 @pytest.mark.parametrize("kind,R,d", [("f32", 32, 3), ("f32", 16, 4), ("bf16", 32, 3), ("f64", 16, 3)])
 def test_sorted_copy_matches_gathered(gpu, kind, R, d):
-    """The mode-sorted record copy changes where records are read from, not the traversal: both
-    kernels sum every row in the same order, so they agree to the rounding of the (at most two
-    per wave chunk) boundary atomics, whose order is not fixed; with and without replacement
-    values, and both match the oracle."""
+    """The storage-ordered record copy changes where records are read from, not the traversal:
+    both kernels sum every row in the same order, so they agree to the rounding of the (at most
+    two per wave chunk) boundary atomics, whose order is not fixed.  The second-mode copy sums
+    each row in another order, so it agrees to rounding.  With and without replacement values
+    (read through the copy's own order array), and every result matches the oracle."""
     import paper_1809_09175_amd as spt
     dims = (900, 700, 60, 30)[:d]
     X = _small(kind, dims, 70_001, (1.1,) * d, seed=77)
     T = _dev_tensor(X, np.float64 if kind == "f64" else np.float32)
     T.permute()
-    T.sort_copy()
     dev, ref = _factors(dims, R, seed=5, kind=kind)
-    y = torch.from_numpy(np.random.default_rng(1).standard_normal(X.nnz).astype(
-        np.float64 if kind == "f64" else np.float32)).cuda()
-    for n in range(d):
-        assert spt.default_tune(T, n, R, dev[0].dtype)["algo"] == "permuted_copy"
-        for vals in (None, y):
-            a = spt.mttkrp(T, dev, n, algo="permuted", vals=vals)
-            b = spt.mttkrp(T, dev, n, algo="permuted_copy", vals=vals)
-            torch.cuda.synchronize()
-            tight = 1e-14 if kind == "f64" else 1e-6
-            assert _relerr(a.cpu().numpy(), b.cpu().numpy().astype(np.float64)) < tight, n
-        V_ref = oracle.mttkrp(X.subs, X.vals, dims, ref, n)
-        assert _relerr(spt.mttkrp(T, dev, n).cpu().numpy(), V_ref) < TOL[kind]
+    vdt = np.float64 if kind == "f64" else np.float32
+    yh = np.random.default_rng(1).standard_normal(X.nnz).astype(vdt)
+    y = torch.from_numpy(yh).cuda()
+    for order in ("storage", "second_mode"):
+        T.sort_copy(order=order)
+        for n in range(d):
+            assert spt.default_tune(T, n, R, dev[0].dtype)["algo"] == "permuted_copy"
+            for vals in (None, y):
+                _log(f"sorted copy {kind} d={d} order={order} n={n} vals={vals is not None}")
+                a = spt.mttkrp(T, dev, n, algo="permuted", vals=vals)
+                b = spt.mttkrp(T, dev, n, algo="permuted_copy", vals=vals)
+                torch.cuda.synchronize()
+                if order == "storage":
+                    tight = 1e-14 if kind == "f64" else 1e-6
+                else:
+                    tight = 1e-13 if kind == "f64" else 1e-5
+                assert _relerr(a.cpu().numpy(), b.cpu().numpy().astype(np.float64)) < tight, n
+                if vals is not None:
+                    V_y = oracle.mttkrp(X.subs, yh.astype(np.float64), dims, ref, n)
+                    assert _relerr(b.cpu().numpy(), V_y) < TOL[kind], (order, n)
+            V_ref = oracle.mttkrp(X.subs, X.vals, dims, ref, n)
+            assert _relerr(spt.mttkrp(T, dev, n).cpu().numpy(), V_ref) < TOL[kind]
     # re-permuting a mode drops its copy; the permuted-copy kernel then reports the state error
     from paper_1809_09175_amd import SptError
     T.permute(0)
     with pytest.raises(SptError) as e:
         spt.mttkrp(T, dev, 0, algo="permuted_copy")
     assert e.value.code == -7
+
+
+@pytest.mark.parametrize("vdt,d,dims", [(np.float32, 3, (900, 700, 60)),
+                                        (np.float32, 4, (50, 700, 700, 9)),
+                                        (np.float64, 3, (5, 1, 3000)),
+                                        (np.float64, 2, (1, 400))])
+def test_second_mode_copy_order_is_exact(gpu, vdt, d, dims):
+    """The second-mode copy of mode n holds the records ordered by (mode-n subscript, mode-m
+    subscript, storage position), m the other mode with the most rows (lowest index among
+    equals): bit-exact against a lexicographic sort on the host, record words included, for
+    every mode at once (the copies laid back to back) and for one mode alone.  Covers a mode of
+    size one (no radix pass: the order is perm_m itself) and duplicate coordinates."""
+    import paper_1809_09175_amd as spt
+    rng = np.random.default_rng(31)
+    P = 40_003
+    subs = np.stack([np.minimum(rng.zipf(1.3, size=P) - 1, I - 1) for I in dims], 1).astype(np.int32)
+    subs[P // 2:P // 2 + 100] = subs[:100]  # duplicate coordinates
+    vals = rng.standard_normal(P).astype(vdt)
+    T = spt.SparseTensor(torch.from_numpy(subs).cuda(), torch.from_numpy(vals).cuda(), dims)
+    T.permute()
+    rw = 4 if d * 4 + vals.itemsize <= 16 else 8
+    expect_rec = np.zeros((P, rw), np.int32)
+    expect_rec[:, :d] = subs
+    if vdt == np.float64:
+        expect_rec[:, rw - 2:] = vals.view(np.int32).reshape(P, 2)
+    else:
+        expect_rec[:, rw - 1] = vals.view(np.int32)
+    one = -(-P * rw * 4 // 256) * 256 + -(-P * 4 // 256) * 256
+    for mode in (-1, d - 1):
+        _log(f"second-mode copy order d={d} dims={dims} mode={mode}")
+        T.sort_copy(mode, order="second_mode")
+        torch.cuda.synchronize()
+        buf = T._copies[mode].cpu().numpy()
+        modes = range(d) if mode == -1 else [mode]
+        assert buf.size == one * len(modes)
+        for k, n in enumerate(modes):
+            others = [m for m in range(d) if m != n]
+            m2 = max(others, key=lambda m: (dims[m], -m))
+            order = np.lexsort((np.arange(P), subs[:, m2], subs[:, n]))
+            got = buf[k * one:k * one + P * rw * 4].view(np.int32).reshape(P, rw)
+            assert np.array_equal(got, expect_rec[order]), (mode, n)
+            qbase = k * one + -(-P * rw * 4 // 256) * 256
+            q = buf[qbase:qbase + P * 4].view(np.int32)
+            assert np.array_equal(q, order.astype(np.int32)), (mode, n)
+    # the second mode must be permuted too
+    T2 = spt.SparseTensor(torch.from_numpy(subs).cuda(), torch.from_numpy(vals).cuda(), dims)
+    T2.permute(0)
+    from paper_1809_09175_amd import SptError
+    with pytest.raises(SptError) as e:
+        T2.sort_copy(0, order="second_mode")
+    assert e.value.code == -7
+    T2.sort_copy(0, order="storage")
 
 
 @pytest.mark.parametrize("kind,R,chunk", [("f32", 32, 64), ("f32", 16, 0), ("bf16", 32, 256),
