@@ -81,7 +81,7 @@ def _sampled_rel_errors(X, dev_outs, ref_factors, rows_per_mode=20, seed=0):
     return max(errs)
 
 
-def bench_skewed4_bf16(spt, datagen, torch, dev, R=32, steps=5):
+def bench_skewed4_bf16(spt, datagen, torch, dev, R=32, steps=10, warmup=2):
     """BF16 vs FP32 factors on the 4-way skewed tensor, all modes, permuted kernel."""
     t0 = time.time()
     X = datagen.skewed4()
@@ -95,8 +95,9 @@ def bench_skewed4_bf16(spt, datagen, torch, dev, R=32, steps=5):
     outs = [torch.empty((I, R), dtype=torch.float32, device=dev) for I in X.dims]
     res = {}
     for name, A in (("fp32", A32), ("bf16", A16)):
-        for n in range(X.d):
-            spt.mttkrp(T, A, n, out=outs[n])
+        for _ in range(warmup):
+            for n in range(X.d):
+                spt.mttkrp(T, A, n, out=outs[n])
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -416,7 +417,8 @@ def main():
         # BF16 factors on the same tensor
         A32 = factors_for(R)
         A16 = [spt.to_bf16(a) for a in A32]
-        b16 = measure(R, "permuted_copy", 5, 1, A=A16)
+        # same step and warmup counts as the FP32 figure it is compared with
+        b16 = measure(R, "permuted_copy", args.steps, max(args.warmup, 2), A=A16)
         extras["bf16_factors_same_tensor"] = {
             "ms_per_step": round(b16["ms_per_step"], 3),
             "speedup_vs_fp32": round(main_res["ms_per_step"] / b16["ms_per_step"], 3)}
