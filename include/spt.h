@@ -149,7 +149,8 @@ int spt_tensor_perm(const spt_tensor *X, int mode, const int32_t **perm, const i
  *                            (4 bytes per entry), used where replacement values are read.
  * Needs spt_tensor_permute(mode) first (SPT_ESTATE otherwise); mode = -1 copies every mode back
  * to back.  ws: device buffer of at least spt_tensor_sorted_copy_bytes(X, mode, order) bytes,
- * 256-byte aligned, caller-owned, kept alive until the copy is dropped or the handle destroyed;
+ * 256-byte aligned (any pointer, NULL included, when that size is 0: an empty tensor),
+ * caller-owned, kept alive until the copy is dropped or the handle destroyed;
  * the second-mode order also uses the tensor's sort scratch.  A later spt_tensor_permute of a
  * mode drops its copy.  With a copy present, SPT_ALGO_AUTO selects SPT_ALGO_PERMUTED_COPY.
  * SPT_EINVAL for an unknown order (and 0 bytes from the size query). */

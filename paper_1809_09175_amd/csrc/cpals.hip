@@ -148,8 +148,9 @@ __global__ __launch_bounds__(kBlock) void k_sum_parts(const double *__restrict__
 // first wavefront alone).  Lane r owns row r of L in registers; row c of L, which lane c wrote
 // to LDS as it computed it, is read into registers with independent LDS broadcasts at the start
 // of column step c, so each step is one dependent chain of register arithmetic; the steps
-// synchronise with wave barriers.  Same column-by-column order and operation order as the textbook algorithm, and no
-// FMA contraction, so the factor follows the plain definition's rounding.
+// synchronise with wave barriers.  Same column-by-column order and operation order as the
+// textbook algorithm, and no FMA contraction, so the factor follows the plain definition's
+// rounding.  Lanes from R on compute on unused rows and store nothing.
 template <int RMAX>
 __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restrict__ grams, int d,
                                                           int n, int R, double *__restrict__ L,

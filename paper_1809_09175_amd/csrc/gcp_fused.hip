@@ -3,7 +3,8 @@
 // gathered through the permutation) computes each entry's model value, the loss derivative y
 // and y's contribution to the mode-n gradient row, an MTTKRP of the derivative tensor with the
 // same segmented reduction as the permuted MTTKRP.  The derivative tensor is never written, and
-// the only gathers are the factor rows the MTTKRP reads anyway plus the mode-n row of the entry.
+// the only gathers are the factor rows the MTTKRP reads anyway plus the mode-n row, which a lane
+// group loads once per run of equal mode-n subscripts.
 // The pass over mode 0 also sums the loss.
 #include "mttkrp_kernels.h"
 

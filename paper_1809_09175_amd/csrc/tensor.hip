@@ -605,7 +605,8 @@ int spt_tensor_sort_copy(spt_tensor *X, int mode, int order, void *ws, size_t ws
     if (X == nullptr || mode < -1 || mode >= X->d) return SPT_EINVAL;
     if (order != SPT_COPY_STORAGE_ORDER && order != SPT_COPY_BY_SECOND_MODE) return SPT_EINVAL;
     const size_t need = spt_tensor_sorted_copy_bytes(X, mode, order);
-    if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < need) return SPT_EWORKSPACE;
+    if (need > 0 && (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < need))
+        return SPT_EWORKSPACE;
     for (int n = 0; n < X->d; ++n) {
         if (mode != -1 && n != mode) continue;
         if (!X->permuted[n]) return SPT_ESTATE;
@@ -641,8 +642,10 @@ int spt_tensor_sort_copy(spt_tensor *X, int mode, int order, void *ws, size_t ws
                                    X->rec, q, X->P, dst);
             SPT_LAUNCH_CHECK();
         }
-        X->srec[n] = dst;
-        X->sperm[n] = q;
+        // an empty tensor's copy holds nothing (and its workspace may be null): the records'
+        // address, never read, marks the copy as present
+        X->srec[n] = (X->P > 0) ? dst : X->rec;
+        X->sperm[n] = (X->P > 0) ? q : X->perm[n];
     }
     return SPT_OK;
 }

@@ -258,7 +258,10 @@ def test_gcp_gradcheck_fp64(gpu):
 
 @pytest.mark.parametrize("loss", ["bernoulli", "gaussian", "poisson", "gamma"])
 @pytest.mark.parametrize("kind", ["f64", "f32"])
-def test_gcp_general_losses(gpu, loss, kind):
+@pytest.mark.parametrize("copies", [False, True])
+def test_gcp_general_losses(gpu, loss, kind, copies):
+    """Weighted losses (the unfused forward and backward; with copies, the backward's MTTKRPs
+    read the derivative values through the second-mode copy's order array)."""
     import paper_1809_09175_amd as spt
     dt = np.float64 if kind == "f64" else np.float32
     X, A = _gcp_case(dt)
@@ -266,6 +269,8 @@ def test_gcp_general_losses(gpu, loss, kind):
         X.vals = (X.vals > 0).astype(dt)
     T = _dev_tensor(X, dt)
     T.permute()
+    if copies:
+        T.sort_copy(order="second_mode")
     rng = np.random.default_rng(4)
     w = (rng.random(X.nnz) + 0.5).astype(dt)
     shift = 0.05 if loss == "gamma" else -0.2  # the Gamma model is a positive mean

@@ -186,6 +186,11 @@ def test_mttkrp_edge_cases(gpu):
         V = spt.mttkrp(T, dev, 1, algo=algo)
         torch.cuda.synchronize()
         assert V.shape == (5, 8) and not V.cpu().numpy().any()
+    for order in ("storage", "second_mode"):
+        T.sort_copy(order=order)  # zero bytes: a null workspace is accepted
+        V = spt.mttkrp(T, dev, 1, algo="permuted_copy")
+        torch.cuda.synchronize()
+        assert V.shape == (5, 8) and not V.cpu().numpy().any()
     # a single entry, a mode of length one, replacement values
     X = datagen.CooTensor(np.array([[3, 0, 2]], np.int32), np.array([2.5], np.float32), (4, 1, 6))
     T = _dev_tensor(X, np.float32)
