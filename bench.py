@@ -431,8 +431,16 @@ def main():
         t_fit = time.perf_counter()
         st.fit()
         fit_ms = (time.perf_counter() - t_fit) * 1e3
+        st.fit(source="mttkrp")  # the handle's first call also sums ||X||^2
+        t_fit = time.perf_counter()
+        st.fit(source="mttkrp")
+        fast_fit_ms = (time.perf_counter() - t_fit) * 1e3
         extras["cp_als_sweep_ms"] = round(sweep_ms, 3)
         extras["cp_fit_ms"] = round(fit_ms, 3)
+        extras["cp_fit_from_mttkrp_ms"] = round(fast_fit_ms, 3)
+        # one iteration as cp_als runs it: a sweep and the fit from the last mode's MTTKRP
+        iter_ms = sweep_ms + fast_fit_ms
+        extras["cp_als_iteration_ms"] = round(iter_ms, 3)
         extras["sort_ms_all_modes"] = round(sort_ms, 3)
         extras["sorted_copy_ms_all_modes"] = round(copy_ms, 3)
         extras["ingest_h2d_ms"] = round(h2d_ms, 1)
@@ -442,9 +450,9 @@ def main():
         extras["sorted_copy_bytes_all_modes"] = int(lib.spt_tensor_sorted_copy_bytes(T.handle, -1, 1))
         extras["tensor_workspace_bytes"] = int(T.ws.numel())
         extras["one_gpu_share_of_8"] = bench_shard_share(spt, torch, T, X, dev, R, shards=8)
-        extras["sort_over_cp_als_iteration"] = round(sort_ms / (sweep_ms + fit_ms), 3)
-        extras["sort_and_copy_over_cp_als_iteration"] = round((sort_ms + copy_ms) / (sweep_ms + fit_ms), 3)
-        log(f"CP-ALS sweep {sweep_ms:.2f} ms, fit {fit_ms:.2f} ms")
+        extras["sort_over_cp_als_iteration"] = round(sort_ms / iter_ms, 3)
+        extras["sort_and_copy_over_cp_als_iteration"] = round((sort_ms + copy_ms) / iter_ms, 3)
+        log(f"CP-ALS sweep {sweep_ms:.2f} ms, fit {fit_ms:.2f} ms (from the MTTKRP {fast_fit_ms:.2f} ms)")
         del st
         # STREAM-style triad on 3 x 1 GiB
         n = 1 << 28

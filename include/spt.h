@@ -276,6 +276,20 @@ int spt_cp_fit(const spt_tensor *X, int R, const void *const *factors, int fdtyp
                const double *lambda, const double *grams, void *ws, size_t ws_bytes,
                double *fit, double *parts, void *stream);
 
+/* The same fit right after spt_cp_als_mode(X, mode, ...) (typically the last mode of a sweep),
+ * without a pass over the entries.  The V that update left in ws is X_(n) times the
+ * Khatri-Rao product of the other, normalised factors, so <X,M> = sum_j lambda_j sum_r
+ * A^(n)(r, j) V(r, j): an I_n x R inner product of the updated factor with the MTTKRP (FP64
+ * sums; V itself carries the MTTKRP's accumulation precision, FP32 for FP32 and BF16 factors).
+ * ||M||^2 as in spt_cp_fit; ||X||^2 is summed from the stored values at the handle's first call
+ * and kept in the handle (the values never change).  Valid only while ws still holds that
+ * update's V and no factor, lambda or Gram changed since: no other call may use ws in between
+ * (spt_cp_fit may: it leaves V alone).  Arguments, synchronisation and outputs as spt_cp_fit;
+ * factors, lambda and grams are the state the mode update left. */
+int spt_cp_fit_after_mode(spt_tensor *X, int mode, int R, const void *const *factors,
+                          int fdtype, const double *lambda, const double *grams, void *ws,
+                          size_t ws_bytes, double *fit, double *parts, void *stream);
+
 /* Model value of every stored entry, m_i = sum_j lambda_j prod_m A^(m)(l_im, j) (eq. (CP)).
  * out: device P values, double for SPT_F64 factors, float otherwise.  lambda may be NULL. */
 int spt_model_values(const spt_tensor *X, int R, const void *const *factors, int fdtype,

@@ -252,6 +252,7 @@ class CPState:
         if nbytes == 0:
             raise SptError(_lib.SPT_EUNSUPPORTED, "spt_cp_workspace_bytes (R must be <= 64)")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self._last_mode = None  # mode whose MTTKRP the workspace holds (for the fast fit)
         for m, f in enumerate(self.factors):
             _lib.check(lib.spt_cp_gram(int(f.shape[0]), self.R, ctypes.c_void_p(f.data_ptr()),
                                        self.fdtype,
@@ -269,6 +270,7 @@ class CPState:
             ctypes.c_void_p(self.lam.data_ptr()), ctypes.c_void_p(self.grams.data_ptr()),
             ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(tune),
             _stream(stream)), "spt_cp_als_mode")
+        self._last_mode = int(n)
 
     def sweep(self, algo="auto", stream=None):
         tune = _tune(algo)
@@ -277,27 +279,40 @@ class CPState:
             ctypes.c_void_p(self.lam.data_ptr()), ctypes.c_void_p(self.grams.data_ptr()),
             ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(tune),
             _stream(stream)), "spt_cp_als_sweep")
+        self._last_mode = self.X.d - 1
 
-    def fit(self, return_parts=False, stream=None):
-        """Synchronising: fit of the current model from the stored entries (FP64)."""
+    def fit(self, return_parts=False, source="entries", stream=None):
+        """Synchronising: fit of the current model.  source="entries": <X,M> from every stored
+        entry's model value (FP64).  source="mttkrp": from the MTTKRP of the last mode update
+        (an I_n x R inner product, no pass over the entries; valid while the factors, weights
+        and Grams are the ones that update left)."""
         f = ctypes.c_double()
         parts = (ctypes.c_double * 3)()
-        _lib.check(_lib.load().spt_cp_fit(
-            self.X.handle, self.R, self._fptrs(), self.fdtype,
-            ctypes.c_void_p(self.lam.data_ptr()), ctypes.c_void_p(self.grams.data_ptr()),
-            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(f), parts,
-            _stream(stream)), "spt_cp_fit")
+        lib = _lib.load()
+        common = (self._fptrs(), self.fdtype, ctypes.c_void_p(self.lam.data_ptr()),
+                  ctypes.c_void_p(self.grams.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                  self.ws.numel(), ctypes.byref(f), parts, _stream(stream))
+        if source == "entries":
+            _lib.check(lib.spt_cp_fit(self.X.handle, self.R, *common), "spt_cp_fit")
+        elif source == "mttkrp":
+            if self._last_mode is None:
+                raise ValueError("fit(source='mttkrp') needs a mode update first")
+            _lib.check(lib.spt_cp_fit_after_mode(self.X.handle, self._last_mode, self.R, *common),
+                       "spt_cp_fit_after_mode")
+        else:
+            raise ValueError(f"unknown fit source {source!r}")
         return (f.value, list(parts)) if return_parts else f.value
 
 
-def cp_als(X: SparseTensor, factors, iters=10, algo="auto", tol=None):
+def cp_als(X: SparseTensor, factors, iters=10, algo="auto", tol=None, fit="mttkrp"):
     """Run CP-ALS sweeps from the given initial factors (updated in place).  Returns the state
-    and the fit after every sweep."""
+    and the fit after every sweep, computed from the last mode's MTTKRP (fit="mttkrp", no pass
+    over the entries) or from the stored entries (fit="entries")."""
     st = CPState(X, factors)
     fits = []
     for _ in range(iters):
         st.sweep(algo)
-        fits.append(st.fit())
+        fits.append(st.fit(source=fit))
         if tol is not None and len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
             break
     return st, fits

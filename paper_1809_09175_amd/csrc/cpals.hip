@@ -1,7 +1,10 @@
 // CP-ALS on the GPU (Sec. 3 defers the algorithm to Kolda & Bader; this is the textbook update):
 // Gram matrices, their Hadamard product, an R x R Cholesky factorisation, row-parallel
-// triangular solves, column normalisation, and the fit computed from the stored entries.
-// All of it in FP64; factors are stored in FP64, FP32 or BF16.
+// triangular solves, column normalisation, and the fit computed from the stored entries (or,
+// after a mode update, from that mode's MTTKRP).  All of it in FP64; factors are stored in
+// FP64, FP32 or BF16.
+#include <algorithm>
+
 #include "mttkrp_kernels.h"
 
 namespace spt {
@@ -9,6 +12,7 @@ namespace spt {
 constexpr int kCpMaxR = 64;
 constexpr int kGramRows = 64;       // rows staged per tile in the Gram kernel
 constexpr int kMaxPartBlocks = 1024;
+constexpr int kModelMaxBlocks = 2048;  // workgroups of the model pass (fit, GCP forward)
 
 struct CpWs {
     size_t V, Y, L, gpart, cpart, misc, total;
@@ -23,8 +27,8 @@ static CpWs cp_layout(int64_t Imax, int R) {
     o += align256((size_t)Imax * R * 8);
     w.L = o;
     o += align256((size_t)R * R * 8);
-    w.gpart = o;
-    o += align256((size_t)kMaxPartBlocks * R * R * 8);
+    w.gpart = o;  // Gram / column partials (R x R per block), or fit partials (2 per block)
+    o += align256((size_t)std::max(kMaxPartBlocks * R * R, 2 * kModelMaxBlocks) * 8);
     w.cpart = o;  // Y^T Y
     o += align256((size_t)R * R * 8);
     w.misc = o;
@@ -537,6 +541,44 @@ __global__ __launch_bounds__(kBlock) void k_fit_final(const double *__restrict__
     }
 }
 
+// ||X||^2 = sum of the squared stored values (FP64): block b's share at part[2b], the slot of
+// the pair layout k_fit_final reads.
+template <int RW, class VT>
+__global__ __launch_bounds__(kBlock) void k_values_sumsq(const int4 *__restrict__ rec, int64_t P,
+                                                         double *__restrict__ part) {
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < P; i += stride) {
+        int w[RW];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) w[k] = reinterpret_cast<const int *>(rec)[i * RW + k];
+        const double x = (double)rec_value<VT, RW>(w);
+        s += x * x;
+    }
+    s = block_sum_f64(s);
+    if (threadIdx.x == 0) part[2 * blockIdx.x] = s;
+}
+
+// <X, M> from the mode-n MTTKRP V (computed from the other, normalised factors with unit
+// weights): sum over r, j of lambda_j A^(n)(r, j) V(r, j), FP64.  Block b's share goes to
+// part[2b + 1]; with have_xx block 0 also stores xx at part[0] and the others 0 at part[2b].
+template <class FT, class AT>
+__global__ __launch_bounds__(kBlock) void k_inner_av(const FT *__restrict__ A,
+                                                     const AT *__restrict__ V,
+                                                     const double *__restrict__ lambda,
+                                                     int64_t len, int R, int have_xx, double xx,
+                                                     double *__restrict__ part) {
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride)
+        s += lambda[i % R] * load_f64(A + i) * (double)V[i];
+    s = block_sum_f64(s);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x + 1] = s;
+        if (have_xx) part[2 * blockIdx.x] = (blockIdx.x == 0) ? xx : 0.0;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_loss_final(const double *__restrict__ part, int nblk,
                                                        double *__restrict__ loss) {
     double s = 0.0;
@@ -580,7 +622,7 @@ static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
     const int chunk = 2048;
     int64_t nchunks = ceil_div(X->P, chunk);
     int64_t nblk = ceil_div(nchunks, kBlock / kWave);
-    if (nblk > 2048) nblk = 2048;
+    if (nblk > kModelMaxBlocks) nblk = kModelMaxBlocks;
     if (nblk < 1) nblk = 1;
     *nblk_out = (int)nblk;
     int G = 8, CPL = 1;
@@ -815,6 +857,72 @@ int spt_cp_fit(const spt_tensor *X, int R, const void *const *factors, int fdtyp
     double h[4];
     SPT_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
     SPT_HIP(hipStreamSynchronize(s));
+    *fit = h[0];
+    if (parts) {
+        parts[0] = h[1];
+        parts[1] = h[2];
+        parts[2] = h[3];
+    }
+    return spt_tensor_status(X, stream);
+}
+
+int spt_cp_fit_after_mode(spt_tensor *X, int mode, int R, const void *const *factors,
+                          int fdtype, const double *lambda, const double *grams, void *ws,
+                          size_t ws_bytes, double *fit, double *parts, void *stream) {
+    if (X == nullptr || mode < 0 || mode >= X->d || R < 1 || R > kCpMaxR || lambda == nullptr ||
+        grams == nullptr || fit == nullptr)
+        return SPT_EINVAL;
+    if (fdtype != SPT_F64 && fdtype != SPT_F32 && fdtype != SPT_BF16) return SPT_EINVAL;
+    int rc = check_factors(X, -1, factors);
+    if (rc) return rc;
+    const CpWs L = cp_layout(max_dim(X), R);
+    if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < L.total) return SPT_EWORKSPACE;
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    const void *V = w + L.V;  // left there by the mode update
+    double *part = reinterpret_cast<double *>(w + L.gpart);
+    double *out = reinterpret_cast<double *>(w + L.misc);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t len = X->dims[mode] * (int64_t)R;
+    const int nblk = (int)std::min<int64_t>(kMaxPartBlocks, std::max<int64_t>(1, ceil_div(len, kBlock)));
+    const bool have_xx = X->xx_valid != 0;
+    if (!have_xx) {
+        if (X->rec_words == 4) {
+            if (X->vdtype == SPT_F64)
+                hipLaunchKernelGGL((k_values_sumsq<4, double>), dim3(nblk), dim3(kBlock), 0, s, X->rec, X->P, part);
+            else
+                hipLaunchKernelGGL((k_values_sumsq<4, float>), dim3(nblk), dim3(kBlock), 0, s, X->rec, X->P, part);
+        } else {
+            if (X->vdtype == SPT_F64)
+                hipLaunchKernelGGL((k_values_sumsq<8, double>), dim3(nblk), dim3(kBlock), 0, s, X->rec, X->P, part);
+            else
+                hipLaunchKernelGGL((k_values_sumsq<8, float>), dim3(nblk), dim3(kBlock), 0, s, X->rec, X->P, part);
+        }
+        SPT_LAUNCH_CHECK();
+    }
+    const double xx = have_xx ? X->xx : 0.0;
+    if (fdtype == SPT_F64)
+        hipLaunchKernelGGL((k_inner_av<double, double>), dim3(nblk), dim3(kBlock), 0, s,
+                           static_cast<const double *>(factors[mode]), static_cast<const double *>(V),
+                           lambda, len, R, (int)have_xx, xx, part);
+    else if (fdtype == SPT_F32)
+        hipLaunchKernelGGL((k_inner_av<float, float>), dim3(nblk), dim3(kBlock), 0, s,
+                           static_cast<const float *>(factors[mode]), static_cast<const float *>(V),
+                           lambda, len, R, (int)have_xx, xx, part);
+    else
+        hipLaunchKernelGGL((k_inner_av<uint16_t, float>), dim3(nblk), dim3(kBlock), 0, s,
+                           static_cast<const uint16_t *>(factors[mode]), static_cast<const float *>(V),
+                           lambda, len, R, (int)have_xx, xx, part);
+    SPT_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(kBlock), 0, s, part, nblk, lambda, grams, X->d,
+                       R, out);
+    SPT_LAUNCH_CHECK();
+    double h[4];
+    SPT_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+    if (!have_xx) {
+        X->xx = h[1];
+        X->xx_valid = 1;
+    }
     *fit = h[0];
     if (parts) {
         parts[0] = h[1];

@@ -35,6 +35,8 @@ struct spt_tensor {
     uint32_t *scan_part; // per-segment partial sums of the counts scan
     double *red;         // reduction scratch (fit, loss): kRedSlots doubles
     int permuted[SPT_MAX_ORDER];
+    double xx;           // ||X||^2 of the stored values, once xx_valid (the values never change)
+    int xx_valid;
 };
 
 namespace spt {

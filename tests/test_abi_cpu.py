@@ -71,6 +71,8 @@ def test_host_argument_checks(lib):
     assert lib.spt_tensor_sorted_copy_bytes(None, -1, 0) == 0
     assert lib.spt_tensor_sorted_copy_bytes(None, 0, 1) == 0
     assert lib.spt_tensor_sort_copy(None, -1, 1, None, 0, None) == -1
+    assert lib.spt_cp_fit_after_mode(None, 0, 8, None, 1, None, None, None, 0, None, None,
+                                     None) == -1
 
 
 def test_workspace_accounting_matches_section5_storage():

@@ -51,7 +51,7 @@ def test_cpals_small_fp64_ten_sweeps(gpu, algo):
     T = _dev_tensor(X, np.float64)
     T.permute()
     if algo == "permuted_copy":
-        T.sort_copy()  # the fit then also runs over the sorted copy
+        T.sort_copy()  # the MTTKRPs then read the sorted record copies
     st = spt.CPState(T, [torch.from_numpy(a.copy()).cuda() for a in A])
     Ao = [a.copy() for a in A]
     lo = np.ones(16)
@@ -143,8 +143,8 @@ def test_cp_mode_update_fp64_ranks(gpu, R):
 
 @pytest.mark.parametrize("copy_mode", [None, 0, 2])
 def test_fit_matches_oracle_fp32_factors(gpu, copy_mode):
-    """Fit from FP32 factors: over the records in storage order, and over a sorted record copy
-    (mode 0 or 2) when one exists."""
+    """Fit from FP32 factors over the stored entries; a permuted mode with a sorted record copy
+    (mode 0 or 2) present leaves it unchanged."""
     import paper_1809_09175_amd as spt
     X = _skewed4_small()
     R = 16
@@ -160,6 +160,85 @@ def test_fit_matches_oracle_fp32_factors(gpu, copy_mode):
                                   st.lam.cpu().numpy(), return_parts=True)
     assert abs(f - f_ref) < 1e-12 * max(1.0, abs(f_ref))
     assert np.allclose(parts, parts_ref, rtol=1e-12)
+
+
+def test_fit_after_mode_fp64_matches_oracle(gpu):
+    """The fit from the last mode's MTTKRP (no pass over the entries) equals the oracle's fit
+    from the entries, every sweep of an FP64 run, and the entry-pass fit of the same state; also
+    right after a single update of a middle mode, and with ||X||^2 served from the handle."""
+    import paper_1809_09175_amd as spt
+    X, A = datagen.cpals_small()
+    T = _dev_tensor(X, np.float64)
+    T.permute()
+    st = spt.CPState(T, [torch.from_numpy(a.copy()).cuda() for a in A])
+    with pytest.raises(ValueError):
+        st.fit(source="mttkrp")
+    Ao = [a.copy() for a in A]
+    lo = np.ones(16)
+    Go = np.stack([oracle.gram(a) for a in Ao])
+    for it in range(6):
+        _log(f"fit after mode, sweep {it}")
+        st.sweep()
+        f_fast, p_fast = st.fit(return_parts=True, source="mttkrp")
+        f_ent, p_ent = st.fit(return_parts=True)
+        Ao, lo, Go = oracle.cp_als_sweep(X.subs, X.vals, X.dims, Ao, lo, Go)
+        f_ref, p_ref = oracle.fit(X.subs, X.vals, X.dims, Ao, lo, return_parts=True)
+        assert abs(f_fast - f_ref) < 1e-12, (it, f_fast, f_ref)
+        assert abs(f_fast - f_ent) < 1e-12
+        assert np.allclose(p_fast, p_ref, rtol=1e-11)
+    st.mode_update(1)
+    Ao, lo, Go = oracle.cp_als_mode(X.subs, X.vals, X.dims, Ao, lo, Go, 1)
+    f_ref = oracle.fit(X.subs, X.vals, X.dims, Ao, lo)
+    assert abs(st.fit(source="mttkrp") - f_ref) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16"])
+def test_fit_after_mode_low_precision(gpu, kind):
+    """FP32 / BF16 factors: the MTTKRP-based fit agrees with the FP64 entry-pass fit of the
+    same state to the FP32 accumulation of V (4-way tensor, R = 16, both after a sweep and
+    after the update of mode 2)."""
+    import paper_1809_09175_amd as spt
+    X = _skewed4_small()
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    T.sort_copy()
+    A32 = datagen.factors(X.dims, 16, seed=4, dtype=np.float32)
+    facs = [torch.from_numpy(a).cuda() for a in A32]
+    if kind == "bf16":
+        facs = [spt.to_bf16(f) for f in facs]
+    st = spt.CPState(T, facs)
+    for step in range(3):
+        _log(f"fit after mode {kind} step {step}")
+        if step < 2:
+            st.sweep()
+        else:
+            st.mode_update(2)
+        f_fast = st.fit(source="mttkrp")
+        f_ent = st.fit()
+        assert abs(f_fast - f_ent) < 1e-5, (step, f_fast, f_ent)
+
+
+def test_fit_rank_one_many_entries(gpu):
+    """R = 1 with 5e6 entries: the entry-pass fit's 2 x ~600 block partials exceed the R x R
+    Gram partial area of R = 1, which the workspace now sizes for both; both fits against the
+    oracle."""
+    import paper_1809_09175_amd as spt
+    rng = np.random.default_rng(12)
+    dims = (3000, 2000, 1000)
+    P = 5_000_000
+    subs = np.stack([rng.integers(0, I, size=P) for I in dims], 1).astype(np.int32)
+    vals = rng.random(P)
+    T = spt.SparseTensor(torch.from_numpy(subs).cuda(), torch.from_numpy(vals).cuda(), dims)
+    T.permute()
+    A = [rng.random((I, 1)) for I in dims]
+    st = spt.CPState(T, [torch.from_numpy(a.copy()).cuda() for a in A])
+    st.mode_update(0)
+    Ao = [a.copy() for a in A]
+    Go = np.stack([oracle.gram(a) for a in Ao])
+    Ao, lo, Go = oracle.cp_als_mode(subs, vals, dims, Ao, np.ones(1), Go, 0)
+    f_ref = oracle.fit(subs, vals, dims, Ao, lo)
+    assert abs(st.fit() - f_ref) < 1e-11
+    assert abs(st.fit(source="mttkrp") - f_ref) < 1e-11
 
 
 def test_model_values(gpu):
