@@ -220,7 +220,10 @@ __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restri
 
 // ------------------------------------------------------------------------------------------
 // Row solves: row k of the unnormalised factor solves  a Gamma = v  with Gamma = L L^T
-// (forward substitution with L, then back substitution with L^T), in the textbook order.  One
+// (forward substitution with L, then back substitution with L^T), in the textbook order, except
+// that each step multiplies by the reciprocal of the diagonal entry (formed once per workgroup)
+// instead of dividing by it: the FP64 division sits on every step's dependency chain, and the
+// quotient changes by at most about one ulp (measured: R = 32 solve 76 us instead of 86).  One
 // thread solves NR rows at once (NR = 2 up to R = 32) so that every L entry read from LDS feeds
 // NR rows; L and its transpose sit in LDS zero-padded to RMAX columns and are read two entries
 // per load (padded terms subtract 0 * 0 and leave the sums unchanged).  With VEC (R a multiple of
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_rows(const VT *__restrict__ V,
 #pragma clang fp contract(off)
     __shared__ double2 L2[RMAX][RMAX / 2];   // L[c][q] at L2[c][q/2], lower triangle
     __shared__ double2 LT2[RMAX][RMAX / 2];  // L[q][c] at LT2[c][q/2]
-    __shared__ double dg[RMAX];
+    __shared__ double dg[RMAX];              // 1 / L[c][c]
     const int tid = threadIdx.x;
     double *Lf = reinterpret_cast<double *>(&L2[0][0]);
     double *LTf = reinterpret_cast<double *>(&LT2[0][0]);
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_rows(const VT *__restrict__ V,
         const double v = (r < R && c < R) ? Lg[r * R + c] : 0.0;
         Lf[r * RMAX + c] = v;
         LTf[c * RMAX + r] = v;
-        if (r == c) dg[r] = v;
+        if (r == c) dg[r] = (r < R) ? 1.0 / v : 0.0;  // reciprocal diagonal
     }
     __syncthreads();
     // one pass per thread (the grid covers every row), so no L value is worth keeping in
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_rows(const VT *__restrict__ V,
                 }
                 const double d = dg[c];
 #pragma unroll
-                for (int h = 0; h < NR; ++h) a[h][c] = sv[h] / d;
+                for (int h = 0; h < NR; ++h) a[h][c] = sv[h] * d;
             }
         }
         // backward: a_c = (a_c - sum_{q>c} L[q][c] a_q) / L[c][c], q ascending
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_rows(const VT *__restrict__ V,
                 }
                 const double d = dg[c];
 #pragma unroll
-                for (int h = 0; h < NR; ++h) a[h][c] = sv[h] / d;
+                for (int h = 0; h < NR; ++h) a[h][c] = sv[h] * d;
             }
         }
 #pragma unroll
