@@ -1,13 +1,14 @@
 """Benchmark: all-mode MTTKRP on the 1e8-entry power-law tensor (500,000 x 500,000 x 20,000,
 Zipf(1.1) subscripts per mode, FP32 values and factors) on one MI355X.
 
-One step = one MTTKRP of every mode (zero V, then the permuted-traversal kernel), R = 32.  The
-metric is effective GB/s under the paper's bandwidth model (bytes per entry = value + d
-subscripts + (d-1) gathered factor rows + one output row), the same byte count for both
-kernels so effective GB/s is proportional to 1/time.  Also reported: the atomic kernel, R = 16
-and 64, the permutation-build cost against one CP-ALS sweep, a STREAM-style triad, the BF16
-factor speedup on the 4-way skewed tensor, the dominant kernel's roofline fraction, and the
-FP64 CPU oracle timed on a bounded sample of the same tensor.
+One step = one MTTKRP of every mode (zero V, then the permuted-traversal kernel over the
+mode-sorted record copies, built beforehand like the permutations), R = 32.  The metric is
+effective GB/s under the paper's bandwidth model (bytes per entry = value + d subscripts + (d-1)
+gathered factor rows + one output row), the same byte count for every kernel so effective GB/s
+is proportional to 1/time.  Also reported: the gather and atomic kernels, R = 16 and 64, the
+permutation and copy build costs against one CP-ALS iteration, a STREAM-style triad, BF16
+factors, the 64-tensor batch, the generalized-CP passes, the dominant kernel's roofline
+fraction, and the FP64 CPU oracle timed on a bounded sample of the same tensor.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
