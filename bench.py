@@ -500,6 +500,12 @@ def main():
                 "kernel": kname + " reading the sorted record copies",
                 "per_launch_model_bytes": per_launch_bytes,
                 "avg_launch_ms": round(avg_launch_ms, 4)}
+    if traffic is not None:
+        # the HBM bytes the counters saw per launch over the same launch time: the physical
+        # share of the HBM peak (model bytes above exceed it because factor rows hit in cache)
+        phys = traffic / (avg_launch_ms * 1e-3) / 1e9
+        roofline["physical_gbs"] = round(phys, 1)
+        roofline["physical_frac"] = round(phys / HBM_PEAK_GBS, 4)
 
     cpu = None
     if not args.no_cpu:
