@@ -1,7 +1,8 @@
 /*
  * spt.h -- C ABI of libspt, the MI355X (gfx950) sparse COO tensor library: per-mode
- * permutations, MTTKRP (atomic and permuted traversal), CP-ALS update, fit and the
- * generalized-CP Poisson loss.
+ * permutations and mode-sorted record copies, MTTKRP (atomic, permuted and privatised
+ * traversals, batched launches), CP-ALS update and fit, generalized-CP losses with their
+ * gradients, and the sampling and Adam steps of stochastic generalized CP.
  *
  * Method: Phipps & Kolda, "Software for Sparse Tensor Decomposition on Emerging Computing
  * Architectures", arXiv 1809.09175.
@@ -25,7 +26,9 @@
  *    spt_tensor_status).
  *  - Thread safety: a tensor handle may be used concurrently by several host threads for
  *    read-only calls (MTTKRP, fit, model values) once its permutations exist; calls that write
- *    into the workspace (create, permute, cp_* steps) must not overlap on one tensor.
+ *    into the workspace or the handle (create, permute, sort_copy, deterministic MTTKRP, cp_*
+ *    steps, and the first spt_cp_fit_after_mode, which stores ||X||^2 in the handle) must not
+ *    overlap on one tensor.
  */
 #ifndef SPT_H
 #define SPT_H
