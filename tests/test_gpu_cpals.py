@@ -162,6 +162,31 @@ def test_fit_matches_oracle_fp32_factors(gpu, copy_mode):
     assert np.allclose(parts, parts_ref, rtol=1e-12)
 
 
+@pytest.mark.parametrize("fit", ["mttkrp", "entries"])
+def test_cp_als_driver(gpu, fit):
+    """cp_als: factors updated in place, one fit per sweep from either source matching the
+    oracle's sweeps, and the tolerance stop ending the run early once the fit settles."""
+    import paper_1809_09175_amd as spt
+    X, A = datagen.cpals_small()
+    T = _dev_tensor(X, np.float64)
+    T.permute()
+    facs = [torch.from_numpy(a.copy()).cuda() for a in A]
+    st, fits = spt.cp_als(T, facs, iters=5, fit=fit)
+    assert len(fits) == 5
+    Ao, lo = [a.copy() for a in A], np.ones(16)
+    Go = np.stack([oracle.gram(a) for a in Ao])
+    for it in range(5):
+        Ao, lo, Go = oracle.cp_als_sweep(X.subs, X.vals, X.dims, Ao, lo, Go)
+        assert abs(fits[it] - oracle.fit(X.subs, X.vals, X.dims, Ao, lo)) < 1e-12, it
+    for m in range(3):
+        assert facs[m].data_ptr() == st.factors[m].data_ptr()  # updated in place
+        assert _relerr(_np(facs[m]), Ao[m]) < 1e-11
+    _, fits2 = spt.cp_als(T, [torch.from_numpy(a.copy()).cuda() for a in A], iters=200,
+                          fit=fit, tol=1e-3)
+    assert 2 <= len(fits2) < 200
+    assert abs(fits2[-1] - fits2[-2]) < 1e-3
+
+
 def test_fit_after_mode_fp64_matches_oracle(gpu):
     """The fit from the last mode's MTTKRP (no pass over the entries) equals the oracle's fit
     from the entries, every sweep of an FP64 run, and the entry-pass fit of the same state; also
