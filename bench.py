@@ -517,8 +517,18 @@ def main():
         for n in range(d):
             oracle.mttkrp(sub_s, sub_v, X.dims, A, n)
         cpu_s = time.perf_counter() - t
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         cpu = {"value": round(S * model_bytes(d, R) * d / cpu_s / 1e9, 3), "unit": "GB/s",
                "cores": 1, "kind": "oracle",
+               "host": f"1 of {os.cpu_count()} logical CPUs, {model}",
                "sample": f"first {S} of {P} entries of the same tensor, all {d} modes, R={R}, "
                          f"FP64 single-threaded ({cpu_s:.1f} s)"}
         log(f"CPU oracle: {cpu['value']} GB/s effective on the sample")
