@@ -109,15 +109,20 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("algo", ["atomic", "permuted"])
+@pytest.mark.parametrize("algo", ["atomic", "permuted", "permuted_copy"])
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-d{len(c[1])}-R{c[4]}-P{c[2]}" for c in CASES])
 def test_mttkrp_parity(gpu, case, algo):
+    """Every case against the oracle: the atomic kernel, the permuted kernel gathering through
+    the permutation, and the permuted kernel over mode-sorted record copies (second-mode order
+    within rows, the default), at a short and a long wave chunk."""
     import paper_1809_09175_amd as spt
     kind, dims, nnz, skew, R = case
     _log(f"mttkrp {kind} dims={dims} nnz={nnz} R={R} algo={algo}")
     X = _small(kind, dims, nnz, skew, seed=nnz + R)
     T = _dev_tensor(X, np.float64 if kind == "f64" else np.float32)
     T.permute()
+    if algo == "permuted_copy":
+        T.sort_copy()
     dev, ref = _factors(dims, R, seed=R, kind=kind)
     lam = np.linspace(0.5, 1.5, R)
     lam_d = torch.from_numpy(lam).cuda()
