@@ -179,19 +179,28 @@ __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restri
     double maxdiag = 0.0;
     for (int k = 0; k < R; ++k) maxdiag = S[k][k] > maxdiag ? S[k][k] : maxdiag;
     const double tol = (double)R * 2.220446049250313e-16 * maxdiag;
-    // Column step c: every lane forms s = S[r][c] - sum_k L[r][k] L[c][k] over all RMAX columns;
-    // the terms from column c on are 0 * 0 (neither row has them yet) and leave s unchanged, so
-    // the sums equal the textbook ones term for term.  Lane c's s is the pivot.
+    // Column step c: every lane forms s = S[r][c] - sum_k L[r][k] L[c][k] over the 8-column chunks
+    // that start before c; the terms from column c on are 0 * 0 (neither row has them yet) and
+    // leave s unchanged, so the sums equal the textbook ones term for term.  Lane c's s is the
+    // pivot.
     double row[RMAX];
 #pragma unroll
     for (int k = 0; k < RMAX; ++k) row[k] = 0.0;
     for (int c = 0; c < R; ++c) {
+        // row c of L so far (LDS broadcasts) and s = S[r][c] - sum_k L[r][k] L[c][k], in chunks
+        // of 8 columns; chunks that start at or after c hold only 0 * 0 terms and are skipped
+        // (c is uniform, so whole chunks are branched over and the sums stay the same)
         double lrow[RMAX];
-#pragma unroll
-        for (int k = 0; k < RMAX; ++k) lrow[k] = Lc[c][k];  // row c of L so far (LDS broadcast)
         double sacc = S[r][c];
 #pragma unroll
-        for (int k = 0; k < RMAX; ++k) sacc -= row[k] * lrow[k];
+        for (int kb = 0; kb < RMAX; kb += 8) {
+            if (kb < c) {
+#pragma unroll
+                for (int k = kb; k < kb + 8; ++k) lrow[k] = Lc[c][k];
+#pragma unroll
+                for (int k = kb; k < kb + 8; ++k) sacc -= row[k] * lrow[k];
+            }
+        }
         if (r == c) {
             double piv = sacc;
             if (!(piv > tol)) {
