@@ -133,7 +133,9 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
     if (G * cpl < R || !cfg_supported(G, cpl)) return SPT_EUNSUPPORTED;
     if (t.nnz_per_wave == 0) {
         // long chunks amortise the chunk-boundary work, but a small tensor needs enough
-        // wavefronts to occupy the GPU: aim for at least ~2048 wave chunks
+        // wavefronts to occupy the GPU: aim for at least ~2048 wave chunks (the permuted launch
+        // may then match the chunk to the device's resident wavefronts: capacity_chunk)
+        t.flags |= kTuneChunkDefaulted;
         const int64_t cap = (lalgo == SPT_ALGO_PERMUTED) ? 4096 : 2048;
         int64_t c = (X->P / 2048) & ~int64_t(63);
         t.nnz_per_wave = (int)(c < 256 ? 256 : (c > cap ? cap : c));
@@ -177,6 +179,9 @@ int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *facto
     a.slot_keys = nullptr;
     a.slot_vals = nullptr;
     a.In = (int)X->dims[mode];
+    a.auto_chunk = (t.flags & kTuneChunkDefaulted) != 0;
+    a.cus = device_cus();
+    a.query_chunk = nullptr;
     a.hbits = table_hbits(t.lanes_per_nnz, t.cols_per_lane, fdtype == SPT_F64 ? 8 : 4,
                           X->rec_words / 4, t.lds_kib);
     if (t.algo == SPT_ALGO_PRIVATIZED) {
@@ -269,7 +274,33 @@ extern "C" int spt_mttkrp_default_tune(const spt_tensor *X, int mode, int R, int
     if (X == nullptr || out == nullptr || mode < 0 || mode >= X->d || R < 1 || R > 256)
         return SPT_EINVAL;
     spt_tune in{algo, 0, 0, 0, 0};
-    return resolve_tune(X, mode, R, fdtype, &in, out);
+    int rc = resolve_tune(X, mode, R, fdtype, &in, out);
+    if (rc) return rc;
+    if ((out->flags & kTuneChunkDefaulted) && X->P > 0 && out->algo == SPT_ALGO_PERMUTED_COPY) {
+        // report the chunk the launch will use (no launch: a query of the dispatch)
+        MttkrpArgs a{};
+        int chunk = out->nnz_per_wave;
+        a.P = X->P;
+        a.R = R;
+        a.n = mode;
+        a.chunk = out->nnz_per_wave;
+        a.algo = out->algo;
+        a.auto_chunk = 1;
+        a.cus = device_cus();
+        a.query_chunk = &chunk;
+        a.srec = X->srec[mode];
+        const void *none[SPT_MAX_ORDER] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        switch (fdtype) {
+            case SPT_F64: rc = launch_mttkrp_f64(a, X->d, none, out->lanes_per_nnz, out->cols_per_lane); break;
+            case SPT_F32: rc = launch_mttkrp_f32(a, X->d, none, out->lanes_per_nnz, out->cols_per_lane); break;
+            case SPT_BF16: rc = launch_mttkrp_bf16(a, X->d, none, out->lanes_per_nnz, out->cols_per_lane); break;
+            default: rc = SPT_EINVAL;
+        }
+        if (rc) return rc;
+        out->nnz_per_wave = chunk;
+    }
+    out->flags &= ~kTuneChunkDefaulted;
+    return SPT_OK;
 }
 
 // ------------------------------------------------------------------------------------------

@@ -787,6 +787,9 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
 // launch dispatch over (order, lane config) for one dtype triple
 // ------------------------------------------------------------------------------------------
 
+// spt_tune.flags bit set by the library (never by callers) when nnz_per_wave took the default
+constexpr int kTuneChunkDefaulted = 1 << 30;
+
 struct MttkrpArgs {
     const int4 *rec;
     const int32_t *perm;
@@ -802,8 +805,28 @@ struct MttkrpArgs {
     int *slot_keys;   // deterministic mode: 2 slots per wave chunk (null: boundary atomics)
     void *slot_vals;
     int In;           // output rows (privatised mode: hbits < 0)
+    int auto_chunk;   // chunk is the default and may be matched to the resident capacity
+    int cus;          // compute units of the device
+    int *query_chunk; // non-null: store the chunk the launch would use, launch nothing
     hipStream_t stream;
 };
+
+// Default wave chunk of the permuted kernel over sorted record copies, for layouts of 4 or more
+// columns per lane (gathering through the permutation prefers the short default): the fewest
+// rounds k of the wavefronts the whole GPU holds at once (cap) whose chunk ceil(P / (k cap)),
+// rounded up to 64 entries, stays within 32768, so the wave count lands just under a whole
+// number of rounds instead of leaving a partial last round.  Measured on MI355X (1e8-entry
+// power-law tensor, R = 32): 32768-entry chunks 3.39 ms, 4096 3.73, 24576 (1.3 rounds) 4.55.
+// Chunks below 8192 keep the default.
+inline int capacity_chunk(int64_t P, int64_t cap, int dflt) {
+    if (cap <= 0) return dflt;
+    for (int64_t k = 1; k <= 1024; ++k) {
+        int64_t c = ceil_div(P, k * cap);
+        c = ceil_div(c, 64) * 64;
+        if (c <= 32768) return c >= 8192 ? (int)c : dflt;
+    }
+    return dflt;
+}
 
 template <class AT>
 inline size_t atomic_smem_bytes(int RQ, int H, int RP) {
@@ -824,9 +847,26 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
     const unsigned grid = (unsigned)ceil_div(a.P, per_block);
     if (grid == 0) return SPT_OK;
     if (a.algo == SPT_ALGO_PERMUTED || a.algo == SPT_ALGO_PERMUTED_COPY) {
-        hipLaunchKernelGGL((k_mttkrp_perm<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock), 0,
+        int chunk = a.chunk;
+        if (a.auto_chunk && a.slot_keys == nullptr && a.srec != nullptr && CPL >= 4) {
+            // resident wavefronts of this instantiation on the whole device (queried once)
+            static const int per_cu = [] {
+                int nb = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &nb, k_mttkrp_perm<D, G, CPL, FT, VT, AT>, kBlock, 0) != hipSuccess)
+                    nb = 0;
+                return nb * (kBlock / kWave);
+            }();
+            chunk = capacity_chunk(a.P, (int64_t)per_cu * a.cus, chunk);
+        }
+        if (a.query_chunk != nullptr) {
+            *a.query_chunk = chunk;
+            return SPT_OK;
+        }
+        const unsigned pgrid = (unsigned)ceil_div(a.P, (int64_t)chunk * (kBlock / kWave));
+        hipLaunchKernelGGL((k_mttkrp_perm<D, G, CPL, FT, VT, AT>), dim3(pgrid), dim3(kBlock), 0,
                            a.stream, a.rec, a.perm, a.srec, a.P, a.n, a.R, A, a.lambda, vovr, V,
-                           a.chunk, a.slot_keys, static_cast<AT *>(a.slot_vals));
+                           chunk, a.slot_keys, static_cast<AT *>(a.slot_vals));
         if (a.slot_keys != nullptr) {
             const int64_t nslots = 2 * ceil_div(a.P, a.chunk);
             hipLaunchKernelGGL((k_det_fixup<AT>), dim3((unsigned)ceil_div(nslots, kBlock / kWave)),
@@ -834,6 +874,10 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
                                static_cast<const AT *>(a.slot_vals), nslots, a.R, V);
         }
     } else {
+        if (a.query_chunk != nullptr) {
+            *a.query_chunk = a.chunk;
+            return SPT_OK;
+        }
         const int H = a.hbits > 0 ? (1 << a.hbits) : 0;
         const size_t smem = a.hbits < 0 ? privatized_smem_bytes<AT>(RecShape<D, VT>::RQ, a.In, G * CPL)
                                         : atomic_smem_bytes<AT>(RecShape<D, VT>::RQ, H, G * CPL);
