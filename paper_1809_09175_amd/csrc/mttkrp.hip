@@ -40,7 +40,7 @@ static bool cfg_supported(int G, int CPL) {
 
 constexpr size_t kPrivatizedLds = 64 * 1024;
 
-static int device_cus() {
+int device_cus() {
     static int cus = 0;
     if (cus == 0) {
         int dev = 0;
