@@ -32,7 +32,7 @@ def log(msg):
 
 
 def model_bytes(d, R, s_val=4, s_idx=4, s_f=4, s_out=4):
-    """Bytes per entry of the paper's MTTKRP bandwidth model (Sec. 6.1), typed per operand."""
+    """Bytes per entry of the paper's MTTKRP bandwidth model (Sec. 7.1), typed per operand."""
     return s_val + d * s_idx + (d - 1) * R * s_f + R * s_out
 
 

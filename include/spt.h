@@ -64,7 +64,7 @@ typedef enum spt_algo {
                                    the order SPT_ALGO_PERMUTED sums them */
     SPT_ALGO_PRIVATIZED = 4 /* storage-order traversal into a per-workgroup LDS copy of the whole
                                output, flushed once per workgroup: the hybrid of atomics and
-                               private copies that Sec. 7 proposes for short modes; only when
+                               private copies that Sec. 8 proposes for short modes; only when
                                I_n x lanes x columns x 4 (8 for FP64) bytes plus 4-8 KiB of
                                staging fit 64 KiB of LDS (SPT_EUNSUPPORTED otherwise) */
 } spt_algo;
@@ -88,7 +88,7 @@ typedef struct spt_tune {
 /* spt_tune.flags.  SPT_TUNE_DETERMINISTIC (permuted algorithms only): the rows a wave chunk
  * shares with its neighbours are not added atomically but parked in two scratch slots per chunk
  * and summed by a second pass in sorted order, so the MTTKRP issues no atomic instruction and V
- * is bit-reproducible from run to run (Sec. 5 notes that the segmented reduction can make
+ * is bit-reproducible from run to run (Sec. 6 notes that the segmented reduction can make
  * atomics unnecessary).  The slots live in the tensor's radix-sort scratch: do not overlap with
  * spt_tensor_permute or another deterministic MTTKRP on the same tensor. */
 #define SPT_TUNE_DETERMINISTIC 1
@@ -106,7 +106,7 @@ int spt_version(void); /* major*10000 + minor*100 + patch */
 
 /* Workspace needed by a tensor of order d (2..5) with the given mode lengths, entry count and
  * value dtype (SPT_F64 or SPT_F32).  It holds the packed entry records, one permutation and one
- * sorted key array per mode (Sec. 5: d extra arrays of P ordinals), the radix-sort scratch and
+ * sorted key array per mode (Sec. 6: d extra arrays of P ordinals), the radix-sort scratch and
  * the status word.  Returns 0 for invalid arguments. */
 size_t spt_tensor_workspace_bytes(int d, const int64_t *dims, int64_t nnz, int vals_dtype);
 
@@ -130,7 +130,7 @@ int spt_tensor_validate(const spt_tensor *X, int64_t *bad_entry, void *stream);
 /* Synchronises `stream` and returns the device status word (then clears it). */
 int spt_tensor_status(const spt_tensor *X, void *stream);
 
-/* Builds the mode-`mode` permutation (mode = -1: every mode), Sec. 5: perm_n is the stable
+/* Builds the mode-`mode` permutation (mode = -1: every mode), Sec. 6: perm_n is the stable
  * order of the entries by their mode-n subscript (ties in storage order) and skey_n the sorted
  * subscripts.  Hand-written LSD radix sort, 8-bit digits.  Enqueued only. */
 int spt_tensor_permute(spt_tensor *X, int mode, void *stream);
@@ -140,7 +140,7 @@ int spt_tensor_permute(spt_tensor *X, int mode, void *stream);
 int spt_tensor_perm(const spt_tensor *X, int mode, const int32_t **perm, const int32_t **skey);
 
 /* Mode-sorted copies of the packed records (a memory-for-bandwidth trade the paper avoided for
- * 12-16 GB GPUs, Sec. 5), so the permuted MTTKRP streams records instead of gathering them.
+ * 12-16 GB GPUs, Sec. 6), so the permuted MTTKRP streams records instead of gathering them.
  * The copy of mode n holds the records grouped by their mode-n subscript in increasing order;
  * within a group, order selects:
  *   SPT_COPY_STORAGE_ORDER   storage order: position q holds record perm_n[q];
@@ -299,7 +299,7 @@ int spt_model_values(const spt_tensor *X, int R, const void *const *factors, int
                      const double *lambda, void *out, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
- * Generalized CP with the Poisson log-link loss (Sec. 7 names generalized CP, for count and
+ * Generalized CP with the Poisson log-link loss (Sec. 8 names generalized CP, for count and
  * binary data, as the next workload): f(x, m) = exp(m) - x m summed over the stored entries
  * (nonzeros and sampled zeros), model m_i = sum_j prod_m A^(m)(l_im, j) (no weights lambda).
  * fdtype SPT_F64 (tensor values F64; w, m, y double) or SPT_F32 (values F32; w, m, y float).

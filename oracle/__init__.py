@@ -11,12 +11,12 @@ Functions and what pins them (tests/test_oracle_pins.py):
   mttkrp        eq. (mttkrp), Sec. 3  -- brute force (dense unfolding x explicit Khatri-Rao),
                                           rank-1 closed form, d=2 sparse-times-dense product,
                                           linearity / duplicate splitting / order invariance
-  perm          Sec. 5 (stable sort)   -- numpy stable argsort, bijection, sortedness
+  perm          Sec. 6 (stable sort)   -- numpy stable argsort, bijection, sortedness
   model_values  eq. (CP), Sec. 3        -- dense Kruskal tensor built with einsum
   fit           eq. (CP), Sec. 3        -- brute-force residual over every cell of a tiny tensor
   cp_als_mode   Sec. 3 (textbook ALS)  -- normal-equation optimality, independent lstsq ALS,
                                           exact low-rank recovery, monotone fit
-  gcp_poisson   Sec. 7 (future work: generalized CP) -- central finite differences, dense loss
+  gcp_poisson   Sec. 8 (future work: generalized CP) -- central finite differences, dense loss
   gcp           the same with Bernoulli-logit and Gaussian losses -- finite differences, dense
                 loss, Gaussian gradient = 2 (model - data) MTTKRP closed form
   bf16_rne      rounding of FP32 to BF16 -- torch's CPU conversion on sampled and boundary bits

@@ -10,11 +10,11 @@
  *   - MTTKRP: eq. (mttkrp), Section 3.  The per-term multiply order follows the paper's
  *     description of the kernel (Section 4.1): start from x_i * lambda_j, then multiply by each
  *     other mode's factor entry in increasing mode order.
- *   - permutation: Section 5 sorts the entries by their mode-n coordinate with a stable sort;
+ *   - permutation: Section 6 sorts the entries by their mode-n coordinate with a stable sort;
  *     here a counting sort (stable by construction).
  *   - CP model and fit: eq. (CP), Section 3.
  *   - CP-ALS: Section 3 defers the algorithm to Kolda & Bader; this is the textbook update.
- *   - GCP Poisson loss: named as future work in Section 7 (generalized CP of Hong, Kolda and
+ *   - GCP Poisson loss: named as future work in Section 8 (generalized CP of Hong, Kolda and
  *     Duersch); loss exp(m) - x m, derivative exp(m) - x.
  * Parity status of every function is listed in the module's Python wrapper header.
  */
@@ -352,7 +352,7 @@ int oracle_bf16_rne_array(int64_t n, const uint32_t *in, uint16_t *out)
 }
 
 /* ---------------------------------------------------------------------------------------------
- * Stochastic generalized CP (GCP-SGD; generalized CP is the workload Sec. 7 names next).
+ * Stochastic generalized CP (GCP-SGD; generalized CP is the workload Sec. 8 names next).
  * ------------------------------------------------------------------------------------------- */
 
 /* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",

@@ -30,7 +30,7 @@ extern "C" {
 int oracle_mttkrp(int d, const int64_t *dims, int64_t P, const int32_t *subs, const double *vals,
                   int n, int R, const double *const *A, const double *lambda, double *V);
 
-/* Stable permutation of the entries by their mode-n coordinate (Section 5): perm[q] is the
+/* Stable permutation of the entries by their mode-n coordinate (Section 6): perm[q] is the
  * storage position of the q-th entry in increasing mode-n order, ties kept in storage order;
  * skey[q] = subs[perm[q]*d + n].  Either output may be NULL. */
 int oracle_perm(int d, const int64_t *dims, int64_t P, const int32_t *subs, int n,

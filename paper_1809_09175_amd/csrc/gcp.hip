@@ -1,4 +1,4 @@
-// Generalized CP with the Poisson log-link loss (Sec. 7 names generalized CP as the next
+// Generalized CP with the Poisson log-link loss (Sec. 8 names generalized CP as the next
 // workload): loss sum_i w_i (exp(m_i) - x_i m_i) over the stored entries, and its gradient with
 // respect to every factor, which is an MTTKRP of the elementwise derivative tensor
 // y_i = w_i (exp(m_i) - x_i) sharing the tensor's subscripts and permutations.

@@ -1,4 +1,4 @@
-// Fused generalized-CP loss and gradient (Sec. 7 names generalized CP as the next workload).
+// Fused generalized-CP loss and gradient (Sec. 8 names generalized CP as the next workload).
 // One pass per mode n over the entries in mode-n order (the sorted record copy, or the records
 // gathered through the permutation) computes each entry's model value, the loss derivative y
 // and y's contribution to the mode-n gradient row, an MTTKRP of the derivative tensor with the

@@ -1,6 +1,6 @@
 // Stochastic generalized CP (GCP-SGD): the stratified sample of an iteration drawn on the device
 // with the Philox4x64-10 counter-based generator (Salmon et al., SC'11), and the Adam update of
-// the factors.  Generalized CP is the workload Sec. 7 names next; the sampled loss and gradient
+// the factors.  Generalized CP is the workload Sec. 8 names next; the sampled loss and gradient
 // come from the existing GCP entry points.
 #include "spt_internal.h"
 

@@ -5,13 +5,13 @@
 //   - a wavefront owns a contiguous chunk of entries (storage order or mode-n sorted order);
 //   - the wave is split into NG = 64/G lane groups; a group handles one entry at a time and its
 //     G lanes hold CPL consecutive rank columns each (the register-resident row slice that the
-//     paper's compile-time polymorphic arrays provide, Sec. 4.3);
+//     paper's compile-time polymorphic arrays provide, Sec. 5);
 //   - 64 entry records are fetched per batch with one 16/32-byte load per lane and staged in
 //     LDS, from where each group reads its entry with one broadcast LDS load;
 //   - U entries are gathered ahead (all factor-row loads issued before any is consumed) so
 //     several row gathers are in flight per lane.
 //
-// k_mttkrp_perm walks the mode-n sorted order (Sec. 5).  Each group owns a contiguous slice of
+// k_mttkrp_perm walks the mode-n sorted order (Sec. 6).  Each group owns a contiguous slice of
 // the wave's chunk and keeps a running row sum while the mode-n subscript is unchanged; a row
 // that starts and ends inside the slice is written with a plain store.  The first and last
 // rows of each slice meet in LDS, where the wave combines them (a segmented reduction across

@@ -1,5 +1,5 @@
 // COO tensor storage for libspt: packing of the caller's subscripts and values into records,
-// and the per-mode permutations of Sec. 5 built by a stable LSD radix sort (8-bit digits,
+// and the per-mode permutations of Sec. 6 built by a stable LSD radix sort (8-bit digits,
 // reduce-then-scan, LDS ranking with wavefront ballots).
 #include <string.h>
 

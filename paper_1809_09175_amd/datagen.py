@@ -4,7 +4,7 @@ This module draws random numbers only; it holds none of the MTTKRP / CP-ALS arit
 the HIP path and the CPU oracle can be fed from it.  All generation is host-side numpy PCG64.
 
 Workload recipes (the paper's real tensors come from the FROSTT collection, which is not
-available; skewed index distributions stand in for real-data contention, Sec. 6.2):
+available; skewed index distributions stand in for real-data contention, Sec. 7.2):
 
   cpals_small   3-way 100 x 80 x 60, 10,000 distinct uniform coordinates, values U(0,1) FP64,
                 factors U(0,1)                                        (seed 1)

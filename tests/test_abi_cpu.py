@@ -76,7 +76,7 @@ def test_host_argument_checks(lib):
 
 
 def test_workspace_accounting_matches_section5_storage():
-    """The permutations cost one P-vector of ordinals per mode (Sec. 5: total (s_r+2 d s_o) P
+    """The permutations cost one P-vector of ordinals per mode (Sec. 6: total (s_r+2 d s_o) P
     with the keys); the workspace holds the records, d permutations and d sorted keys."""
     from paper_1809_09175_amd import _lib
     lib = _lib.load()

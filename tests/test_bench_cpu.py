@@ -1,6 +1,6 @@
 """Host-side pieces of bench.py: the FP64 row evaluation behind its accuracy figure agrees with
 the oracle, the model-byte formula gives the per-entry figures of the paper's bandwidth model
-(Sec. 6.1, typed per operand), and a run on more than one GPU is refused with a message."""
+(Sec. 7.1, typed per operand), and a run on more than one GPU is refused with a message."""
 import subprocess
 import sys
 from pathlib import Path
