@@ -249,8 +249,10 @@ int spt_batch_destroy(spt_batch *B);
  *   Gamma = Hadamard product of G_m, m != n            (FP64, R x R)
  *   Gamma = L L^T (Cholesky; a pivot <= R * eps * max diag(Gamma) sets SPT_ESINGULAR)
  *   row k of A^(n) solves A^(n)(k,:) Gamma = V(k,:)     (FP64 forward/back substitution)
- *   lambda_j = ||A^(n)(:,j)||_2, columns with lambda_j > 0 divided by lambda_j, then stored in
- *   fdtype (BF16: round to nearest even)
+ *   lambda_j = ||A^(n)(:,j)||_2, columns with lambda_j > 0 divided by lambda_j (in FP64), then
+ *   stored in fdtype: FP32 by the ordinary FP64 -> FP32 conversion, BF16 by rounding the FP64
+ *   value to nearest even in a single step (no FP32 intermediate, so no double rounding; the
+ *   rule of spt_f64_to_bf16)
  *   G_n = A^(n)^T A^(n) from the stored values         (FP64)
  * factors: host array of d device pointers (I_m x R, fdtype), A^(n) overwritten.
  * lambda: device R doubles (overwritten).  grams: device d x R x R doubles, G_m for every mode
@@ -269,6 +271,14 @@ int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fd
 int spt_cp_als_sweep(spt_tensor *X, int R, void *const *factors, int fdtype, double *lambda,
                      double *grams, void *ws, size_t ws_bytes, const spt_tune *tune,
                      void *stream);
+
+/* Device pointer (*Y) to the FP64 solution that the last spt_cp_als_mode(X, n, ...) left in ws:
+ * I_n x R row-major doubles, the rows solving A(k,:) Gamma = V(k,:) before normalisation, so the
+ * stored factor is Y(k, j) / lambda_j (Y(k, j) where lambda_j = 0) rounded to fdtype.  For
+ * checking the precision of the stored factor; valid until the next call that uses ws.  No
+ * device work.  SPT_EWORKSPACE if ws is shorter than spt_cp_workspace_bytes(X, R). */
+int spt_cp_solution(const spt_tensor *X, int R, const void *ws, size_t ws_bytes,
+                    const double **Y);
 
 /* Fit of the model M = sum_j lambda_j a_j^(1) o ... o a_j^(d) (eq. (CP)) from the stored
  * entries: fit = 1 - sqrt(max(0, ||X||^2 - 2<X,M> + ||M||^2)) / ||X|| with ||X||^2 and <X,M>
@@ -377,6 +387,13 @@ int spt_scale_values(const void *src, void *dst, int64_t n, int dtype, const dou
 /* FP32 -> BF16 bit patterns, round to nearest, ties to even; NaN stays a quiet NaN with its
  * sign.  in: device n floats; out: device n uint16. */
 int spt_f32_to_bf16(const float *in, uint16_t *out, int64_t n, void *stream);
+
+/* FP64 -> BF16 bit patterns, round to nearest, ties to even, in a single rounding (the value is
+ * narrowed to FP32 with round-to-odd first, which keeps the final rounding correct); NaN maps to
+ * the quiet NaN 0x7fc0 with its sign; magnitudes at or past the midpoint between the largest
+ * finite BF16 and 2^128 give infinity.  The CP-ALS BF16 factor store uses the same rounding.
+ * in: device n doubles; out: device n uint16. */
+int spt_f64_to_bf16(const double *in, uint16_t *out, int64_t n, void *stream);
 
 /* STREAM-style triad a[i] = b[i] + s * c[i] over n floats (device), for measuring achievable
  * HBM bandwidth. */

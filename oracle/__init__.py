@@ -20,6 +20,8 @@ Functions and what pins them (tests/test_oracle_pins.py):
   gcp           the same with Bernoulli-logit and Gaussian losses -- finite differences, dense
                 loss, Gaussian gradient = 2 (model - data) MTTKRP closed form
   bf16_rne      rounding of FP32 to BF16 -- torch's CPU conversion on sampled and boundary bits
+  bf16_rne_f64  rounding of FP64 to BF16 in one step -- bf16_rne on every FP64 value that is an
+                FP32, exact rational arithmetic (fractions) on random and tie-adjacent values
 """
 from __future__ import annotations
 
@@ -253,6 +255,14 @@ def bf16_rne(x):
     bits = a.view(np.uint32) if a.dtype == np.float32 else np.ascontiguousarray(a, np.uint32)
     out = np.empty(bits.shape, dtype=np.uint16)
     _check(_load().oracle_bf16_rne_array(ctypes.c_int64(bits.size), _p(bits), _p(out)))
+    return out
+
+
+def bf16_rne_f64(x):
+    """FP64 array -> uint16 BF16 bit patterns, rounded once (no FP32 step)."""
+    a = np.ascontiguousarray(x, np.float64)
+    out = np.empty(a.shape, dtype=np.uint16)
+    _check(_load().oracle_bf16_rne_f64_array(ctypes.c_int64(a.size), _p(a), _p(out)))
     return out
 
 

@@ -351,6 +351,40 @@ int oracle_bf16_rne_array(int64_t n, const uint32_t *in, uint16_t *out)
     return ORACLE_OK;
 }
 
+uint16_t oracle_bf16_rne_f64(double v)
+{
+    const uint16_t sign = signbit(v) ? 0x8000u : 0u;
+    if (isnan(v)) return (uint16_t)(sign | 0x7fc0u);
+    const double a = fabs(v);
+    if (isinf(a)) return (uint16_t)(sign | 0x7f80u);
+    if (a == 0.0) return sign;
+    /* a = f 2^e with f in [0.5, 1): BF16 keeps 8 significant bits, so its step in this binade
+     * is 2^(e-8), but never finer than the subnormal step 2^-133 */
+    int e;
+    frexp(a, &e);
+    const int qe = (e - 8 < -133) ? -133 : e - 8;
+    const double q = ldexp(1.0, qe);
+    const double k = floor(a / q); /* a / q < 256: exact */
+    const double lo = k * q, hi = lo + q;
+    const double dlo = a - lo, dhi = hi - a; /* exact: multiples of a's ulp below 2^46 of them */
+    double pick;
+    if (dlo < dhi) pick = lo;
+    else if (dhi < dlo) pick = hi;
+    else pick = (fmod(k, 2.0) == 0.0) ? lo : hi; /* tie: even last bit */
+    if (pick >= ldexp(1.0, 128)) return (uint16_t)(sign | 0x7f80u);
+    const float pf = (float)pick; /* at most 8 significant bits inside the FP32 range: exact */
+    uint32_t bits;
+    memcpy(&bits, &pf, sizeof bits);
+    return (uint16_t)(sign | (bits >> 16));
+}
+
+int oracle_bf16_rne_f64_array(int64_t n, const double *in, uint16_t *out)
+{
+    if (n < 0 || (n > 0 && (in == NULL || out == NULL))) return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n; ++i) out[i] = oracle_bf16_rne_f64(in[i]);
+    return ORACLE_OK;
+}
+
 /* ---------------------------------------------------------------------------------------------
  * Stochastic generalized CP (GCP-SGD; generalized CP is the workload Sec. 8 names next).
  * ------------------------------------------------------------------------------------------- */

@@ -109,6 +109,14 @@ int oracle_adam(int64_t n, double *x, const double *g, double *m, double *v, dou
 uint16_t oracle_bf16_rne(uint32_t f32_bits);
 int oracle_bf16_rne_array(int64_t n, const uint32_t *in, uint16_t *out);
 
+/* FP64 -> BF16 round to nearest, ties to even, in a single rounding (no FP32 step): the value
+ * is compared exactly with its two neighbouring BF16 values (8 significant bits, subnormal step
+ * 2^-133); half a step or more past the largest finite BF16 gives infinity.  NaN maps to the
+ * quiet NaN 0x7fc0 with the same sign.  The BF16 factor store of a CP-ALS update rounds its
+ * FP64 solution this way. */
+uint16_t oracle_bf16_rne_f64(double v);
+int oracle_bf16_rne_f64_array(int64_t n, const double *in, uint16_t *out);
+
 #ifdef __cplusplus
 }
 #endif

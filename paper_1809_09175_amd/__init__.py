@@ -213,14 +213,17 @@ def mttkrp(X: SparseTensor, factors, mode: int, lam=None, algo="auto", lanes=0, 
 
 
 def to_bf16(x: torch.Tensor, stream=None) -> torch.Tensor:
-    """FP32 -> BF16 (round to nearest even) with the library's kernel."""
+    """FP32 or FP64 -> BF16 (round to nearest even; FP64 in a single rounding) with the
+    library's kernels."""
     _dev_check(x, "x")
-    if x.dtype != torch.float32:
-        raise ValueError("x must be float32")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise ValueError("x must be float32 or float64")
+    x = x.contiguous()
     out = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device)
-    _lib.check(_lib.load().spt_f32_to_bf16(ctypes.c_void_p(x.data_ptr()),
-                                           ctypes.c_void_p(out.data_ptr()), x.numel(),
-                                           _stream(stream)), "spt_f32_to_bf16")
+    name = "spt_f32_to_bf16" if x.dtype == torch.float32 else "spt_f64_to_bf16"
+    _lib.check(getattr(_lib.load(), name)(ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), x.numel(),
+                                          _stream(stream)), name)
     return out
 
 
@@ -271,6 +274,20 @@ class CPState:
             ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), ctypes.byref(tune),
             _stream(stream)), "spt_cp_als_mode")
         self._last_mode = int(n)
+
+    def solution(self) -> torch.Tensor:
+        """The FP64 solution rows (I_n x R, before normalisation and storage rounding) of the
+        last mode update, as a view into the workspace (valid until the next call using it)."""
+        if self._last_mode is None:
+            raise SptError(_lib.SPT_ESTATE, "CPState.solution: no mode update yet")
+        y = ctypes.c_void_p()
+        _lib.check(_lib.load().spt_cp_solution(self.X.handle, self.R,
+                                                ctypes.c_void_p(self.ws.data_ptr()),
+                                                self.ws.numel(), ctypes.byref(y)),
+                   "spt_cp_solution")
+        off = y.value - self.ws.data_ptr()
+        I = int(self.X.dims[self._last_mode])
+        return self.ws[off:off + I * self.R * 8].view(torch.float64).view(I, self.R)
 
     def sweep(self, algo="auto", stream=None):
         tune = _tune(algo)

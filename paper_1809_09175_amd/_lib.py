@@ -55,6 +55,7 @@ SIGNATURES = {
     "spt_cp_gram": (_c_i, [_c_i64, _c_i, _c_p, _c_i, _c_p, _c_p, _c_sz, _c_p]),
     "spt_cp_als_mode": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p, _c_p]),
     "spt_cp_als_sweep": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p, _c_p]),
+    "spt_cp_solution": (_c_i, [_c_p, _c_i, _c_p, _c_sz, _c_p]),
     "spt_cp_fit": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p, _c_p, _c_p]),
     "spt_cp_fit_after_mode": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p,
                                      _c_p, _c_p]),
@@ -85,6 +86,7 @@ SIGNATURES = {
                              ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_i64,
                              ctypes.c_double, _c_p]),
     "spt_f32_to_bf16": (_c_i, [_c_p, _c_p, _c_i64, _c_p]),
+    "spt_f64_to_bf16": (_c_i, [_c_p, _c_p, _c_i64, _c_p]),
     "spt_stream_triad": (_c_i, [_c_p, _c_p, _c_p, ctypes.c_float, _c_i64, _c_p]),
 }
 

@@ -45,7 +45,7 @@ __device__ __forceinline__ double load_f64(const FT *p) {
 
 template <class FT>
 __device__ __forceinline__ void store_from_f64(FT *p, double v) {
-    if constexpr (sizeof(FT) == 2) *reinterpret_cast<uint16_t *>(p) = f32_to_bf16_rne((float)v);
+    if constexpr (sizeof(FT) == 2) *reinterpret_cast<uint16_t *>(p) = f64_to_bf16_rne(v);
     else *p = (FT)v;
 }
 
@@ -834,6 +834,15 @@ int spt_cp_als_sweep(spt_tensor *X, int R, void *const *factors, int fdtype, dou
         int rc = spt_cp_als_mode(X, n, R, factors, fdtype, lambda, grams, ws, ws_bytes, tune, stream);
         if (rc) return rc;
     }
+    return SPT_OK;
+}
+
+int spt_cp_solution(const spt_tensor *X, int R, const void *ws, size_t ws_bytes,
+                    const double **Y) {
+    if (X == nullptr || R < 1 || R > kCpMaxR || Y == nullptr) return SPT_EINVAL;
+    const CpWs L = cp_layout(max_dim(X), R);
+    if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < L.total) return SPT_EWORKSPACE;
+    *Y = reinterpret_cast<const double *>(static_cast<const uint8_t *>(ws) + L.Y);
     return SPT_OK;
 }
 

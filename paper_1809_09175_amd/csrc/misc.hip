@@ -1,4 +1,5 @@
-// Precision and measurement helpers: FP32 -> BF16 rounding and a STREAM-style triad.
+// Precision and measurement helpers: FP32 -> BF16 and FP64 -> BF16 rounding and a STREAM-style
+// triad.
 #include "spt_internal.h"
 
 namespace spt {
@@ -8,6 +9,13 @@ __global__ __launch_bounds__(kBlock) void k_f32_to_bf16(const float *__restrict_
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
         out[i] = f32_to_bf16_rne(in[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_f64_to_bf16(const double *__restrict__ in,
+                                                        uint16_t *__restrict__ out, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+        out[i] = f64_to_bf16_rne(in[i]);
 }
 
 // Each thread handles kTriadUnroll float4 elements, strided by the block size so every load and
@@ -59,6 +67,16 @@ extern "C" int spt_f32_to_bf16(const float *in, uint16_t *out, int64_t n, void *
     int64_t blocks = ceil_div(n, kBlock);
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)blocks), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), in, out, n);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
+extern "C" int spt_f64_to_bf16(const double *in, uint16_t *out, int64_t n, void *stream) {
+    if (n < 0 || (n > 0 && (in == nullptr || out == nullptr))) return SPT_EINVAL;
+    if (n == 0) return SPT_OK;
+    int64_t blocks = ceil_div(n, kBlock);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_f64_to_bf16, dim3((unsigned)blocks), dim3(kBlock), 0,
                        static_cast<hipStream_t>(stream), in, out, n);
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }

@@ -95,6 +95,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     return (uint16_t)((x + 0x7fffu + lsb) >> 16);
 }
 
+// FP64 -> BF16, round to nearest even in one rounding.  The value is first narrowed to FP32
+// with round-to-odd (toward zero, then the last bit set when anything was cut off); FP32 carries
+// 16 more bits than BF16 at every exponent, subnormals included, so the following
+// round-to-nearest-even to BF16 gives the correctly rounded result of the original double
+// (Boldo and Melquiond's round-to-odd rule).  NaN -> the quiet NaN 0x7fc0 with the sign.
+__device__ __forceinline__ uint16_t f64_to_bf16_rne(double v) {
+    if (v != v) return (uint16_t)(((uint64_t)__double_as_longlong(v) >> 48 & 0x8000u) | 0x7fc0u);
+    uint32_t b = __float_as_uint((float)v);
+    if (fabs((double)__uint_as_float(b)) > fabs(v)) b -= 1u;  // magnitude one step toward zero
+    if ((double)__uint_as_float(b) != v) b |= 1u;
+    return f32_to_bf16_rne(__uint_as_float(b));
+}
+
 __device__ __forceinline__ void atomic_add_f(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f(double *p, double v) { unsafeAtomicAdd(p, v); }
 

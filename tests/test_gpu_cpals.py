@@ -111,6 +111,16 @@ def test_cp_mode_update_low_precision(gpu, kind):
         # the Gram is of the stored (rounded) factor, in FP64
         stored = _np(st.factors[n])
         assert _relerr(st.grams[n].cpu().numpy(), stored.T @ stored) < 1e-12
+        # the stored factor is the FP64 solution over lambda, rounded once to the storage type:
+        # bit-exact against numpy's FP64 -> FP32 conversion / the oracle's FP64 -> BF16 rounding
+        Y = st.solution().cpu().numpy()
+        lam = st.lam.cpu().numpy()
+        a = np.where(lam > 0, Y / np.where(lam > 0, lam, 1.0), Y)
+        if kind == "bf16":
+            bits = st.factors[n].view(torch.int16).cpu().numpy().view(np.uint16)
+            assert np.array_equal(bits, oracle.bf16_rne_f64(a)), n
+        else:
+            assert np.array_equal(st.factors[n].cpu().numpy(), a.astype(np.float32)), n
 
 
 @pytest.mark.parametrize("R", [5, 20, 40, 64])

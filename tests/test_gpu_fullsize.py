@@ -57,7 +57,7 @@ def test_skewed4_full_size_bf16_and_fp32(gpu):
     a32 = [a.astype(np.float32) for a in datagen.factors(X.dims, R, 11, np.float64)]
     ref = [a.astype(np.float64) for a in a32]
     dev32 = [torch.from_numpy(a).cuda() for a in a32]
-    devbf = [t.to(torch.bfloat16) for t in dev32]
+    devbf = [spt.to_bf16(t) for t in dev32]
     for n in range(X.d):
         rows = _rows(X, n, 30, seed=n)
         s, v = _entries_of(X, n, rows)

@@ -41,6 +41,10 @@ MUTANTS = [
     ("unstable perm", "for (int64_t i = 0; i < P; ++i) {\n        int32_t k = subs[i * d + n];",
      "for (int64_t i = P - 1; i >= 0; --i) {\n        int32_t k = subs[i * d + n];"),
     ("bf16 ties away", "? hi_bits : lo_bits; /* tie", "? lo_bits : hi_bits; /* tie"),
+    ("bf16 f64 rounds twice", "const double a = fabs(v);", "const double a = (double)(float)fabs(v);"),
+    ("bf16 f64 no subnormal step", "const int qe = (e - 8 < -133) ? -133 : e - 8;",
+     "const int qe = e - 8;"),
+    ("bf16 f64 ties odd", "pick = (fmod(k, 2.0) == 0.0) ? lo : hi;", "pick = (fmod(k, 2.0) == 0.0) ? hi : lo;"),
 ]
 
 CHECKS = [
@@ -57,6 +61,7 @@ CHECKS = [
     (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="gaussian")),
     (pins.test_gcp_losses_dense_and_finite_differences, dict(loss="gamma")),
     (pins.test_bf16_rne_matches_torch_on_samples_and_boundaries, {}),
+    (pins.test_bf16_rne_f64_matches_exact_rounding_and_fp32_rounding, {}),
     (pins.test_philox_matches_numpy_philox, {}),
     (pins.test_gcp_sample_is_unbiased_and_uniform, {}),
     (pins.test_adam_constant_gradient_closed_form, {}),

@@ -310,6 +310,74 @@ def test_bf16_rne_matches_torch_on_samples_and_boundaries():
     assert oracle.bf16_rne(np.array([0x7F7F0000], np.uint32))[0] == 0x7F7F
 
 
+def _bf16_table():
+    """Every finite non-negative BF16 value as a double, indexed by its bit pattern
+    (0x0000 .. 0x7f7f), followed by 2^128, the value that stands for infinity when rounding."""
+    bits = (np.arange(0, 0x7F80, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+    return np.concatenate([bits, [2.0 ** 128]])
+
+
+def _bf16_nearest_exact(values):
+    """Nearest BF16 pattern to each finite double by exact rational arithmetic over the table of
+    all BF16 values: the two neighbours come from a search in the table, the distances are
+    Fractions, a tie picks the even pattern."""
+    from fractions import Fraction
+    table = _bf16_table()
+    out = []
+    for v in values:
+        a = abs(float(v))
+        sign = 0x8000 if np.signbit(v) else 0
+        if a >= 2.0 ** 128:
+            out.append(sign | 0x7F80)
+            continue
+        i = int(np.searchsorted(table, a, side="right")) - 1
+        if table[i] == a:
+            out.append(sign | i)
+            continue
+        dlo = Fraction(a) - Fraction(float(table[i]))
+        dhi = Fraction(float(table[i + 1])) - Fraction(a)
+        k = i if dlo < dhi else i + 1 if dhi < dlo else (i if i % 2 == 0 else i + 1)
+        out.append(sign | k)
+    return np.array(out, dtype=np.uint16)
+
+
+def _bf16_f64_cases(rng, n_random=6000):
+    """Random doubles over the whole BF16 range (subnormals and overflow included), values at
+    and one double-ulp beside every kind of BF16 midpoint, and the special values."""
+    e = rng.integers(-150, 130, size=n_random)
+    rnd = rng.random(n_random) * np.ldexp(1.0, e) * np.where(rng.random(n_random) < 0.5, -1, 1)
+    table = _bf16_table()
+    idx = rng.integers(0, 0x7F7F, size=3000)
+    mids = (table[idx] + table[idx + 1]) / 2          # exact: one more bit than BF16 carries
+    near = np.concatenate([mids, np.nextafter(mids, np.inf), np.nextafter(mids, -np.inf)])
+    special = np.array([0.0, -0.0, np.inf, -np.inf, 2.0 ** 128, np.finfo(np.float64).max,
+                        float(np.finfo(np.float32).max), 2.0 ** -134, 2.0 ** -133, 2.0 ** -150,
+                        5e-324, 1.0 + 2.0 ** -8 + 2.0 ** -30, 1.0 + 2.0 ** -8])
+    return np.concatenate([rnd, near, -near[:500], special])
+
+
+def test_bf16_rne_f64_matches_exact_rounding_and_fp32_rounding():
+    rng = np.random.default_rng(52)
+    # 1. every double that is an FP32 value rounds as the FP32 rounding does
+    bits = rng.integers(0, 1 << 32, size=1 << 20, dtype=np.uint64).astype(np.uint32)
+    f = bits.view(np.float32)
+    finite = ~np.isnan(f)
+    assert np.array_equal(oracle.bf16_rne_f64(f[finite].astype(np.float64)),
+                          oracle.bf16_rne(bits[finite]))
+    # 2. exact rational rounding over the table of every BF16 value
+    v = _bf16_f64_cases(rng)
+    assert np.array_equal(oracle.bf16_rne_f64(v), _bf16_nearest_exact(v))
+    # 3. one rounding, not two: 1 + 2^-8 + 2^-30 lies above the midpoint 1 + 2^-8, to which an
+    # FP32 step would round it first (and the tie would then go down to 1)
+    x = np.array([1.0 + 2.0 ** -8 + 2.0 ** -30])
+    assert oracle.bf16_rne_f64(x)[0] == 0x3F81
+    assert oracle.bf16_rne(x.astype(np.float32))[0] == 0x3F80
+    # 4. NaN: quiet, sign kept
+    nan = np.array([np.nan, -np.nan, np.frombuffer(np.uint64(0x7FF0000000000001).tobytes(), np.float64)[0]])
+    got = oracle.bf16_rne_f64(nan)
+    assert list(got) == [0x7FC0, 0xFFC0, 0x7FC0]
+
+
 @pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian", "gamma"])
 def test_gcp_losses_dense_and_finite_differences(loss):
     rng = np.random.default_rng(43)
