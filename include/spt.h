@@ -289,6 +289,19 @@ int spt_cp_fit(const spt_tensor *X, int R, const void *const *factors, int fdtyp
                const double *lambda, const double *grams, void *ws, size_t ws_bytes,
                double *fit, double *parts, void *stream);
 
+/* spt_cp_fit for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): no workspace argument and no allocation.
+ * The per-workgroup partial sums go to a fixed scratch array inside the library (about 32 KiB,
+ * one copy per GPU, held until the process ends), looked up for the current device at the
+ * first call on it: `stream` must belong to the current device.  Every call on one GPU shares
+ * that array, so calls that overlap on one GPU (other threads, other streams) race; nothing in
+ * it needs clearing between calls.  Same arguments (without ws), result and synchronisation as
+ * spt_cp_fit; SPT_EWORKSPACE if the tensor needs more partial sums than the array holds (not
+ * reachable at present: the pass uses at most 2048 workgroups). */
+int spt_cp_fit_noalloc(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                       const double *lambda, const double *grams, double *fit, double *parts,
+                       void *stream);
+
 /* The same fit right after spt_cp_als_mode(X, mode, ...) (typically the last mode of a sweep),
  * without a pass over the entries.  The V that update left in ws is X_(n) times the
  * Khatri-Rao product of the other, normalised factors, so <X,M> = sum_j lambda_j sum_r

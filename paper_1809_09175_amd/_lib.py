@@ -56,6 +56,7 @@ SIGNATURES = {
     "spt_cp_als_mode": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p, _c_p]),
     "spt_cp_als_sweep": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p, _c_p]),
     "spt_cp_solution": (_c_i, [_c_p, _c_i, _c_p, _c_sz, _c_p]),
+    "spt_cp_fit_noalloc": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "spt_cp_fit": (_c_i, [_c_p, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p, _c_p, _c_p]),
     "spt_cp_fit_after_mode": (_c_i, [_c_p, _c_i, _c_i, _c_p, _c_i, _c_p, _c_p, _c_p, _c_sz, _c_p,
                                      _c_p, _c_p]),

@@ -4,6 +4,7 @@
 // after a mode update, from that mode's MTTKRP).  All of it in FP64; factors are stored in
 // FP64, FP32 or BF16.
 #include <algorithm>
+#include <mutex>
 
 #include "mttkrp_kernels.h"
 
@@ -629,15 +630,21 @@ static void model_layout(int R, int *G, int *CPL) {
     *CPL = 1;
 }
 
+constexpr int kModelChunk = 2048;  // entries per wavefront chunk of the model pass
+
+// workgroups of the model pass over P entries (each writes one pair of partial sums)
+static int model_blocks(int64_t P) {
+    int64_t nblk = ceil_div(ceil_div(P, kModelChunk), kBlock / kWave);
+    if (nblk > kModelMaxBlocks) nblk = kModelMaxBlocks;
+    return (int)(nblk < 1 ? 1 : nblk);
+}
+
 template <int D, class FT, class VT, class CT, int KIND>
 static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
                           const double *lambda, const CT *w, void *mout, double *part,
                           int *nblk_out, hipStream_t s, int loss) {
-    const int chunk = 2048;
-    int64_t nchunks = ceil_div(X->P, chunk);
-    int64_t nblk = ceil_div(nchunks, kBlock / kWave);
-    if (nblk > kModelMaxBlocks) nblk = kModelMaxBlocks;
-    if (nblk < 1) nblk = 1;
+    const int chunk = kModelChunk;
+    const int64_t nblk = model_blocks(X->P);
     *nblk_out = (int)nblk;
     int G = 8, CPL = 1;
     model_layout(R, &G, &CPL);
@@ -748,6 +755,69 @@ static int launch_solve(const VT *V, int64_t I, int R, const double *L, double *
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }
 
+// Fit from the stored entries: the model pass writes one (sum x^2, sum x m) pair per workgroup
+// into part, k_fit_final reduces them with ||M||^2 into out[0..3], which is copied to the host.
+static int fit_from_entries(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                            const double *lambda, const double *grams, double *part, double *out,
+                            double *fit, double *parts, hipStream_t s) {
+    if ((fdtype == SPT_F64) != (X->vdtype == SPT_F64)) return SPT_EUNSUPPORTED;
+    int nblk = 0, rc;
+    switch (fdtype) {
+        case SPT_F64:
+            rc = launch_model<double, double, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
+            break;
+        case SPT_F32:
+            rc = launch_model<float, float, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
+            break;
+        case SPT_BF16:
+            rc = launch_model<uint16_t, float, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
+            break;
+        default: return SPT_EINVAL;
+    }
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(kBlock), 0, s, part, nblk, lambda, grams, X->d,
+                       R, out);
+    SPT_LAUNCH_CHECK();
+    double h[4];
+    SPT_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
+    SPT_HIP(hipStreamSynchronize(s));
+    *fit = h[0];
+    if (parts) {
+        parts[0] = h[1];
+        parts[1] = h[2];
+        parts[2] = h[3];
+    }
+    return spt_tensor_status(X, s);
+}
+
+// Scratch of spt_cp_fit_noalloc, for callers that cannot allocate device memory: the model
+// pass's partial pairs (at most kModelMaxBlocks of them) and the four result words.  One copy
+// per GPU, held until the process ends; every call on a GPU uses it, so calls that overlap on
+// one GPU race.  Host code never passes the symbol itself to a kernel or a copy: it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kFitScratchDoubles = 2 * (size_t)kModelMaxBlocks + 4;
+static __device__ __align__(256) double scratch[kFitScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+// Address of this GPU's scratch, looked up once per device with that device current.
+static int fit_scratch_ptr(double **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SPT_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return SPT_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return SPT_EHIP;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SPT_OK;
+}
+
 }  // namespace spt
 
 using namespace spt;
@@ -855,38 +925,28 @@ int spt_cp_fit(const spt_tensor *X, int R, const void *const *factors, int fdtyp
     if (rc) return rc;
     const CpWs L = cp_layout(max_dim(X), R);
     if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < L.total) return SPT_EWORKSPACE;
-    if ((fdtype == SPT_F64) != (X->vdtype == SPT_F64)) return SPT_EUNSUPPORTED;
     uint8_t *w = static_cast<uint8_t *>(ws);
-    double *part = reinterpret_cast<double *>(w + L.gpart);
-    double *out = reinterpret_cast<double *>(w + L.misc);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    int nblk = 0;
-    switch (fdtype) {
-        case SPT_F64:
-            rc = launch_model<double, double, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
-            break;
-        case SPT_F32:
-            rc = launch_model<float, float, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
-            break;
-        case SPT_BF16:
-            rc = launch_model<uint16_t, float, double, KIND_FIT>(X, R, factors, lambda, nullptr, nullptr, part, &nblk, s);
-            break;
-        default: return SPT_EINVAL;
-    }
+    return fit_from_entries(X, R, factors, fdtype, lambda, grams,
+                            reinterpret_cast<double *>(w + L.gpart),
+                            reinterpret_cast<double *>(w + L.misc), fit, parts,
+                            static_cast<hipStream_t>(stream));
+}
+
+int spt_cp_fit_noalloc(const spt_tensor *X, int R, const void *const *factors, int fdtype,
+                       const double *lambda, const double *grams, double *fit, double *parts,
+                       void *stream) {
+    if (X == nullptr || R < 1 || R > kCpMaxR || grams == nullptr || fit == nullptr)
+        return SPT_EINVAL;
+    int rc = check_factors(X, -1, factors);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_fit_final, dim3(1), dim3(kBlock), 0, s, part, nblk, lambda, grams, X->d,
-                       R, out);
-    SPT_LAUNCH_CHECK();
-    double h[4];
-    SPT_HIP(hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
-    SPT_HIP(hipStreamSynchronize(s));
-    *fit = h[0];
-    if (parts) {
-        parts[0] = h[1];
-        parts[1] = h[2];
-        parts[2] = h[3];
-    }
-    return spt_tensor_status(X, stream);
+    // partial pairs of the model pass, then the four result words
+    if ((size_t)2 * model_blocks(X->P) + 4 > kFitScratchDoubles) return SPT_EWORKSPACE;
+    double *sp = nullptr;
+    rc = fit_scratch_ptr(&sp);
+    if (rc) return rc;
+    return fit_from_entries(X, R, factors, fdtype, lambda, grams, sp,
+                            sp + kFitScratchDoubles - 4, fit, parts,
+                            static_cast<hipStream_t>(stream));
 }
 
 int spt_cp_fit_after_mode(spt_tensor *X, int mode, int R, const void *const *factors,
