@@ -55,7 +55,9 @@ typedef enum spt_dtype { SPT_F64 = 0, SPT_F32 = 1, SPT_BF16 = 2 } spt_dtype;
 
 typedef enum spt_algo {
     SPT_ALGO_AUTO = 0,     /* library choice (tuned table, else the default heuristic) */
-    SPT_ALGO_ATOMIC = 1,   /* storage-order traversal, LDS-combined partial rows + atomics */
+    SPT_ALGO_ATOMIC = 1,   /* storage-order traversal in tiles of up to 1024 entries, each tile
+                              sorted by output row in LDS and summed per row, then one atomic
+                              per distinct row and column of the tile */
     SPT_ALGO_PERMUTED = 2, /* mode-sorted traversal through the permutation (records gathered),
                               wave segmented reduction */
     SPT_ALGO_PERMUTED_COPY = 3, /* the same traversal reading a mode-sorted copy of the records
@@ -73,16 +75,16 @@ typedef enum spt_algo {
  * lanes_per_nnz lanes evaluates one entry, each lane holding cols_per_lane consecutive rank
  * columns; the product must cover R and cols_per_lane must divide R.  Compiled (lanes, cols)
  * pairs: (4,4) (4,8) (8,1) (8,2) (8,4) (8,8) (16,1) (16,2) (16,4) (16,8) (32,1) (32,2) (64,1)
- * (64,2) (64,4).  nnz_per_wave: entries one wavefront walks (a multiple of 64). */
+ * (64,2) (64,4).  nnz_per_wave: entries one wavefront walks (a multiple of 64); the atomic
+ * algorithm gives each workgroup 4 x nnz_per_wave entries rounded up to whole sorted tiles. */
 typedef struct spt_tune {
     int32_t algo;
     int32_t lanes_per_nnz;
     int32_t cols_per_lane;
     int32_t nnz_per_wave;
     int32_t flags;   /* SPT_TUNE_DETERMINISTIC: see below */
-    int32_t lds_kib; /* atomic algorithm: LDS budget of the per-workgroup combining table in KiB,
-                        at most 64; the table takes the largest power-of-two slot count that fits.
-                        0 = default: at most 128 slots within 64 KiB */
+    int32_t lds_kib; /* reserved: 0 .. 64 accepted (SPT_EINVAL otherwise), no effect on any
+                        algorithm */
 } spt_tune;
 
 /* spt_tune.flags.  SPT_TUNE_DETERMINISTIC (permuted algorithms only): the rows a wave chunk

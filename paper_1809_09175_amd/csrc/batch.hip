@@ -20,7 +20,7 @@ struct BatchItem {
     int64_t P;
     int64_t unit0;   // first work unit of this item (a unit = 4 wave chunks = one workgroup)
     int64_t vwords;  // 32-bit words of V
-    int32_t n, R, cfg, chunk, hbits, pad;
+    int32_t n, R, cfg, chunk;
 };
 
 // (algo, order, lanes per entry, columns per lane) combinations compiled into the batched
@@ -70,12 +70,18 @@ __device__ __forceinline__ void batch_unit(int4 *smem4, const BatchItem &it, int
             perm_wave_chunk<D, G, CPL, FT, float, float, kBatchUnroll>(sm[wave], it.rec, it.perm, it.srec, it.P, it.n,
                                                          it.R, A, nullptr, nullptr, V, it.chunk, c0);
     } else {
-        atomic_block_unit<D, G, CPL, FT, float, float, kBatchUnroll>(smem4, it.rec, it.P, it.n, it.R, A, nullptr,
-                                                       nullptr, V, it.chunk, it.hbits, 0, bc0);
+        using SM = AtomicTileShared<D, G, CPL, float, float>;
+        const int64_t bc1 = bc0 + (int64_t)(kBlock / kWave) * it.chunk;
+        atomic_tile_range<D, G, CPL, FT, float, float, kBatchUnroll>(
+            *reinterpret_cast<SM *>(smem4), it.rec, it.n, it.R, A, nullptr, nullptr, V, bc0,
+            bc1 < it.P ? bc1 : it.P);
     }
 }
 
-template <class FT>
+// ATOMIC = false compiles the permuted configurations only: the atomic path's tile sort raises
+// the kernel's register demand (which every configuration then pays, in spills), so a batch
+// whose products are all permuted runs the lighter kernel.
+template <class FT, bool ATOMIC>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_mttkrp_batched(const BatchItem *__restrict__ items,
                                                            int nitems, int64_t total_units,
                                                            unsigned long long *counter) {
@@ -95,8 +101,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         lo = __builtin_amdgcn_readfirstlane(lo);
         const BatchItem &it = items[lo];
         switch (it.cfg) {
-#define SPT_CFG_CASE(i, a, d, g, c) \
-    case i: batch_unit<a, d, g, c, FT>(smem4, it, u); break;
+#define SPT_CFG_CASE(i, a, d, g, c)                                   \
+    case i:                                                           \
+        if constexpr (ATOMIC || (a) == SPT_ALGO_PERMUTED)               \
+            batch_unit<a, d, g, c, FT>(smem4, it, u);                 \
+        break;
             SPT_BATCH_CONFIGS(SPT_CFG_CASE)
 #undef SPT_CFG_CASE
             default: break;
@@ -142,16 +151,17 @@ static int batch_cfg_index(int algo, int d, int G, int CPL) {
     return -1;
 }
 
-static size_t batch_smem_for(int cfg, int *hbits) {
-    const BatchCfg &c = kBatchCfgs[cfg];
-    const int rq = 1;  // 3-way FP32 records are 16 bytes
-    if (c.algo == SPT_ALGO_PERMUTED) {
-        *hbits = 0;
-        return (size_t)(kBlock / kWave) * perm_shared_bytes(c.G, c.CPL, rq, 4);
+static size_t batch_smem_for(int cfg) {
+    switch (cfg) {
+#define SPT_CFG_SMEM(i, a, d, g, c)                                                       \
+    case i:                                                                               \
+        return (a) == SPT_ALGO_PERMUTED                                                   \
+                   ? (size_t)(kBlock / kWave) * perm_shared_bytes(g, c, 1, 4)             \
+                   : atomic_tile_smem_bytes<d, g, c, float, float>();
+        SPT_BATCH_CONFIGS(SPT_CFG_SMEM)
+#undef SPT_CFG_SMEM
+        default: return 0;
     }
-    const int hb = table_hbits(c.G, c.CPL, 4, rq, 0);
-    *hbits = hb;
-    return atomic_smem_bytes<float>(rq, 1 << hb, c.G * c.CPL);
 }
 
 extern "C" {
@@ -181,6 +191,7 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         return SPT_EWORKSPACE;
     std::vector<BatchItem> h(nitems);
     int64_t units = 0;
+    bool any_atomic = false;
     size_t smem = 0;
     for (int i = 0; i < nitems; ++i) {
         const spt_tensor *X = tensors[i];
@@ -195,6 +206,7 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         if (t.flags & SPT_TUNE_DETERMINISTIC) return SPT_EUNSUPPORTED;
         const int kalgo = (t.algo == SPT_ALGO_PERMUTED_COPY) ? SPT_ALGO_PERMUTED : t.algo;
         const int cfg = batch_cfg_index(kalgo, X->d, t.lanes_per_nnz, t.cols_per_lane);
+        any_atomic = any_atomic || kalgo == SPT_ALGO_ATOMIC;
         if (cfg < 0) return SPT_EUNSUPPORTED;
         BatchItem &b = h[i];
         memset(&b, 0, sizeof b);
@@ -210,9 +222,7 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         b.R = R;
         b.cfg = cfg;
         b.chunk = t.nnz_per_wave;
-        int hb = 0;
-        const size_t sm = batch_smem_for(cfg, &hb);
-        b.hbits = hb;
+        const size_t sm = batch_smem_for(cfg);
         smem = sm > smem ? sm : smem;
         units += ceil_div(X->P, (int64_t)(kBlock / kWave) * t.nnz_per_wave);
     }
@@ -242,10 +252,12 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu = 0;
     hipError_t oe = hipSuccess;
-    if (fdtype == SPT_F32)
-        oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mttkrp_batched<float>, kBlock, smem);
-    else
-        oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mttkrp_batched<uint16_t>, kBlock, smem);
+    const void *kfn = fdtype == SPT_F32
+                          ? (any_atomic ? (const void *)k_mttkrp_batched<float, true>
+                                        : (const void *)k_mttkrp_batched<float, false>)
+                          : (any_atomic ? (const void *)k_mttkrp_batched<uint16_t, true>
+                                        : (const void *)k_mttkrp_batched<uint16_t, false>);
+    oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kBlock, smem);
     if (oe != hipSuccess || per_cu < 1) per_cu = 1;
     int64_t grid = (int64_t)cus * per_cu;
     if (grid > units) grid = units;
@@ -254,12 +266,12 @@ int spt_batch_create(spt_batch **out, int nitems, const spt_tensor *const *tenso
         goto fail;
     hipLaunchKernelGGL(k_batch_zero, dim3(B->zero_blocks, nitems), dim3(kBlock), 0,
                        B->capture_stream, B->d_items, B->d_counter);
-    if (fdtype == SPT_F32)
-        hipLaunchKernelGGL(k_mttkrp_batched<float>, dim3((unsigned)grid), dim3(kBlock), smem,
-                           B->capture_stream, B->d_items, nitems, units, B->d_counter);
-    else
-        hipLaunchKernelGGL(k_mttkrp_batched<uint16_t>, dim3((unsigned)grid), dim3(kBlock), smem,
-                           B->capture_stream, B->d_items, nitems, units, B->d_counter);
+    {
+        void *args[] = {&B->d_items, &nitems, &units, &B->d_counter};
+        if (hipLaunchKernel(kfn, dim3((unsigned)grid), dim3(kBlock), args, smem,
+                            B->capture_stream) != hipSuccess)
+            goto fail;
+    }
     if (hipStreamEndCapture(B->capture_stream, &B->graph) != hipSuccess) goto fail;
     if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess) goto fail;
     *out = B;

@@ -182,13 +182,12 @@ int launch_mttkrp(const spt_tensor *X, int mode, int R, const void *const *facto
     a.auto_chunk = (t.flags & kTuneChunkDefaulted) != 0;
     a.cus = device_cus();
     a.query_chunk = nullptr;
-    a.hbits = table_hbits(t.lanes_per_nnz, t.cols_per_lane, fdtype == SPT_F64 ? 8 : 4,
-                          X->rec_words / 4, t.lds_kib);
+    a.privatized = 0;
     if (t.algo == SPT_ALGO_PRIVATIZED) {
         // privatised output: about two workgroups per CU, each adding a long contiguous range
         // into its LDS copy of V, so every row is flushed to HBM only once per workgroup
         a.algo = SPT_ALGO_ATOMIC;
-        a.hbits = -1;
+        a.privatized = 1;
         int64_t blocks = 2 * (int64_t)device_cus();
         const int64_t minb = ceil_div(X->P, (int64_t)(kBlock / kWave) * 64);
         if (blocks > minb) blocks = minb;

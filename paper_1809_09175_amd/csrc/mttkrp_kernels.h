@@ -18,11 +18,9 @@
 // its groups); only the chunk's first and last rows, which neighbouring waves may share, are
 // added atomically.  No LDS table and no barrier beyond the wavefront.
 //
-// k_mttkrp_atomic walks storage order.  Each product row is added into a per-workgroup LDS
-// hash table keyed by output row (claimed with LDS compare-and-swap, short linear probe); rows
-// that find no slot go straight to global atomics.  At the end the workgroup adds every table
-// row to V with one global atomic per column.  This stages partial sums in LDS so a hot output
-// row receives one global atomic per workgroup instead of one per entry.
+// k_mttkrp_atomic walks storage order in tiles; each tile's entries are sorted by output row in
+// LDS and summed per row like the permuted kernel's chunks, so every distinct row of a tile
+// receives one global atomic per column (see the kernel's own description below).
 #pragma once
 
 #include "spt_internal.h"
@@ -325,20 +323,6 @@ inline size_t perm_shared_bytes(int G, int CPL, int RQ, int at_bytes) {
     return (b + 15) / 16 * 16;
 }
 
-// log2 of the slot count of the atomic kernel's LDS combining table: the largest power of two
-// whose slots (G * CPL accumulators and a key each) fit an LDS budget of lds_kib KiB minus the
-// record staging buffer; without a budget, at most 128 slots within 64 KiB (on a 1e8-entry Zipf
-// tensor at R = 16/32/64, larger tables lost more in resident workgroups per CU than they won).
-inline int table_hbits(int G, int CPL, int at_bytes, int RQ, int lds_kib) {
-    const int staging = (kBlock / kWave) * kWave * RQ * 16;
-    const int budget = (lds_kib > 0 ? lds_kib : 64) * 1024 - staging;
-    const int cap = (lds_kib > 0) ? 12 : 7;
-    const int per_slot = G * CPL * at_bytes + 4;
-    int hb = 0;
-    while (hb < cap && (2 << hb) * per_slot <= budget) ++hb;
-    return hb;
-}
-
 // LDS of one wavefront in the permuted kernel: the staged records of the current batch and the
 // boundary partial rows (first and last row of every lane group's slice).
 template <int D, int G, int CPL, class VT, class AT>
@@ -624,44 +608,332 @@ __global__ __launch_bounds__(kBlock) void k_mttkrp_perm(
                                            chunk, c0, slot_keys, slot_vals);
 }
 
-// Slot of output row k in a workgroup's LDS hash table of H = 2^hbits keys (-1 = free): found or
-// claimed within four linear probes from a multiplicative hash, else -1 (the caller then adds
-// to V directly).  Claims are never released during the workgroup's pass.
-__device__ __forceinline__ int table_slot(int *hkeys, int H, int hbits, int k) {
-    uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - hbits);
-    for (int probe = 0; probe < 4; ++probe) {
-        const int cur = __hip_atomic_load(&hkeys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (cur == k) return (int)h;
-        if (cur == -1) {
-            const int old = atomicCAS(&hkeys[h], -1, k);
-            if (old == -1 || old == k) return (int)h;
-        }
-        h = (h + 1) & (uint32_t)(H - 1);
-    }
-    return -1;
+// ------------------------------------------------------------------------------------------
+// Atomic MTTKRP over storage order (the paper's atomic kernels, Fig. mttkrp_alg and
+// Fig. mttkrp_array), with the partial rows combined inside the workgroup before they reach V.
+//
+// A workgroup takes a tile of T consecutive entries in storage order (T = 1024, fewer where the
+// staging would not fit 64 KiB of LDS):
+//   1. the tile's records are read with coalesced loads and staged in LDS;
+//   2. the tile's mode-n subscripts are sorted in LDS (a bitonic network over (subscript, tile
+//      position) pairs: T / 256 pairs per thread, the compare-exchanges between a thread's own
+//      pairs in registers, the others through LDS with a wavefront barrier, or a workgroup
+//      barrier for the strides that span wavefronts), so the entries of each output row are
+//      adjacent;
+//   3. each wavefront walks a quarter of the sorted tile as the permuted kernel walks its chunk:
+//      lane groups keep a running row sum while the subscript is unchanged, the first and last
+//      rows of every group meet in LDS, then the first and last rows of every wavefront;
+//   4. every distinct row of the tile is added to V with one global atomic per column.
+// So no row receives more than one atomic per tile: a hot row's FP32 sum in V collects
+// P / T pre-summed terms instead of one per entry (with per-entry atomics, rows of a
+// million entries of the 1e8-entry power-law tensor drifted beyond the FP32 tolerance).
+// ------------------------------------------------------------------------------------------
+
+// Entries sorted together: the largest of 1024, 512, 256 whose staging (records, keys,
+// positions) and partial rows fit 64 KiB of LDS.  Measured on the 1e8-entry power-law tensor
+// (all modes, R = 16 / 32 / 64): 1024-entry tiles 12.9 / 27.3 / 52.3 ms, 2048 (two workgroups
+// per CU for lack of LDS) 20.5 / 31.7 / 52.1 ms, 512 17.9 / 34.3 / 68.8 ms.
+constexpr int atomic_tile_for(int RQ, int G, int CPL, int at_bytes) {
+    const int fixed = (512 * CPL + 8 * G * CPL) * at_bytes + 8 * (kWave / G) * 4 + 64;
+    int t = 1024;
+    while (t > 256 && t * (16 * RQ + 6) + fixed > 64 * 1024) t >>= 1;
+    return t;
 }
 
-// One workgroup processes storage positions [bc0, bc0 + 4 chunk) (one chunk per wavefront)
-// through the LDS table in smem4.  Every thread of the workgroup must call it.
+template <int D, int G, int CPL, class VT, class AT>
+struct AtomicTileShared {
+    static constexpr int RQ = RecShape<D, VT>::RQ, NG = kWave / G, NW = kBlock / kWave;
+    static constexpr int T = atomic_tile_for(RQ, G, CPL, (int)sizeof(AT));
+    static constexpr int E = T / kBlock;      // sorted positions per thread
+    static constexpr int WS = T / NW;         // sorted positions per wavefront
+    int4 rec[T * RQ];                // the tile's records, in storage order
+    int key[T];                      // mode-n subscripts, sorted in place
+    uint16_t pos[T];                 // tile position of each sorted subscript
+    AT part[NW][2 * NG][G * CPL];    // first / last row of every lane group
+    int pkey[NW][2 * NG];
+    AT wpart[2 * NW][G * CPL];       // first / last row of every wavefront
+    int wkey[2 * NW];
+};
+
+template <int D, int G, int CPL, class VT, class AT>
+constexpr size_t atomic_tile_smem_bytes() {
+    return (sizeof(AtomicTileShared<D, G, CPL, VT, AT>) + 15) / 16 * 16;
+}
+
+// compare-exchange for a bitonic stage: the pair at sorted position p keeps the smaller key when
+// it is the lower position of an ascending block (or the upper one of a descending block)
+__device__ __forceinline__ void bitonic_take(int &k, int &q, int ko, int qo, bool take_min) {
+    const bool swap = take_min ? (ko < k) : (ko > k);
+    k = swap ? ko : k;
+    q = swap ? qo : q;
+}
+
+// Sorts sm.key[0..T) (with sm.pos) ascending.  Thread t holds positions E t .. E t + E - 1.
+template <class SM>
+__device__ __forceinline__ void tile_sort(SM &sm) {
+    constexpr int E = SM::E, T = SM::T;
+    const int base = threadIdx.x * E;
+    int k[E], q[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        k[i] = sm.key[base + i];
+        q[i] = base + i;
+    }
+    for (int size = 2; size <= T; size <<= 1) {
+        for (int stride = size >> 1; stride >= E; stride >>= 1) {
+            // partners live in other threads: publish, then read the partner's pair
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                sm.key[base + i] = k[i];
+                sm.pos[base + i] = (uint16_t)q[i];
+            }
+            const bool block_wide = stride >= SM::WS;
+            if (block_wide) __syncthreads(); else wave_sync();
+            int ko[E], qo[E];
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int p = base + i, o = p ^ stride;
+                ko[i] = sm.key[o];
+                qo[i] = sm.pos[o];
+            }
+            // the next stage overwrites these slots: every reader must be done first (within a
+            // wavefront the reads above complete before any later write is issued)
+            if (block_wide) __syncthreads();
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const int p = base + i;
+                const bool asc = (p & size) == 0, lower = (p & stride) == 0;
+                bitonic_take(k[i], q[i], ko[i], qo[i], asc == lower);
+            }
+        }
+        // strides below E: pairs inside this thread's eight positions
+#pragma unroll
+        for (int stride = E / 2; stride > 0; stride >>= 1) {
+            if (stride >= size) continue;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                if (i & stride) continue;
+                const int j = i + stride;
+                const bool asc = ((base + i) & size) == 0;
+                const bool sw = asc ? (k[j] < k[i]) : (k[j] > k[i]);
+                const int tk = k[i], tq = q[i];
+                k[i] = sw ? k[j] : k[i];
+                q[i] = sw ? q[j] : q[i];
+                k[j] = sw ? tk : k[j];
+                q[j] = sw ? tq : q[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        sm.key[base + i] = k[i];
+        sm.pos[base + i] = (uint16_t)q[i];
+    }
+    __syncthreads();
+}
+
+// Combines the partial rows parts[0..cnt) (keys ks, -1 = none) of one lane group's columns in
+// sorted order: runs of equal keys are summed.  Runs in between the first and the last are added
+// to V with one atomic per column; the first run goes to (first_out, *first_key) and the last
+// run, when it differs from the first, to (last_out, *last_key) -- or, with FINAL, to V as well.
+// Called by the G lanes of one group.
+template <bool FINAL, int CPL, class AT, class PA>
+__device__ __forceinline__ void combine_runs(const PA &parts, const int *ks, int cnt, int col0,
+                                             bool colok, int gl, AT *__restrict__ V, int R,
+                                             AT *first_out, int *first_key, AT *last_out,
+                                             int *last_key) {
+    int ck = -1;
+    bool first_run = true;
+    AT acc[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[c] = 0;
+    for (int e = 0; e < cnt; ++e) {
+        const int ke = ks[e];
+        if (ke < 0) continue;
+        if (ke != ck) {
+            if (ck >= 0) {
+                if (first_run && !FINAL) {
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) first_out[col0 + c] = acc[c];
+                    if (gl == 0) *first_key = ck;
+                } else if (colok) {
+                    atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, acc);
+                }
+                first_run = false;
+            }
+            ck = ke;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc[c] = 0;
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] += parts[e][col0 + c];
+    }
+    if constexpr (FINAL) {
+        if (ck >= 0 && colok) atomic_cols<AT, CPL>(V + (int64_t)ck * R + col0, acc);
+    } else {
+        if (gl == 0) {
+            *last_key = -1;
+            if (first_run) *first_key = ck;
+        }
+        if (ck >= 0) {
+            AT *dst = first_run ? first_out : last_out;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) dst[col0 + c] = acc[c];
+            if (!first_run && gl == 0) *last_key = ck;
+        }
+    }
+}
+
+// One workgroup processes the storage positions [r0, r1) tile by tile.  Every thread of the
+// workgroup must call it.
 template <int D, int G, int CPL, class FT, class VT, class AT, int UMAX = 64>
-__device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__restrict__ rec,
-                                                  int64_t P, int n, int R, const FactorSet<FT> &A,
+__device__ __forceinline__ void atomic_tile_range(AtomicTileShared<D, G, CPL, VT, AT> &sm,
+                                                  const int4 *__restrict__ rec, int n, int R,
+                                                  const FactorSet<FT> &A,
                                                   const double *__restrict__ lambda,
                                                   const VT *__restrict__ vovr,
-                                                  AT *__restrict__ V, int chunk, int hbits,
-                                                  int In,
-                                                  int64_t bc0) {
+                                                  AT *__restrict__ V, int64_t r0, int64_t r1) {
+    using SM = AtomicTileShared<D, G, CPL, VT, AT>;
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
-    constexpr int RP = G * CPL;
+    constexpr int NG = SM::NG, NW = SM::NW, T = SM::T;
+    constexpr int S = SM::WS / NG;  // sorted positions per lane group
     constexpr int U0 = UnrollFor<KERNEL_ATOMIC, G, CPL, FT>::value;
     constexpr int U = U0 < UMAX ? U0 : UMAX;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane / G, gl = lane % G;
+    const int col0 = gl * CPL;
+    const bool colok = col0 < R;
+    const uint32_t rowbytes = (uint32_t)R * sizeof(FT);
+    const uint32_t colbytes = colok ? (uint32_t)col0 * sizeof(FT) : 0u;
+    const OtherModes<D> om = other_modes<D>(A, n);
+    AT lam[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+        lam[c] = (lambda != nullptr && colok) ? (AT)lambda[col0 + c] : (AT)1;
+
+    for (int64_t t0 = r0; t0 < r1; t0 += T) {
+        const int valid = (int)((r1 - t0) < T ? (r1 - t0) : T);
+        // 1. stage the tile (coalesced), subscripts to sort; past the end: sentinel keys that
+        // sort last and are never processed
+#pragma unroll
+        for (int r = 0; r < SM::E; ++r) {
+            const int e = tid + r * kBlock;
+            int k = 0x7fffffff;
+            if (e < valid) {
+                const int4 *src = rec + (t0 + e) * RQ;
+                sm.rec[e * RQ] = load_stream(src);
+                if constexpr (RQ == 2) sm.rec[e * RQ + 1] = load_stream(src + 1);
+                if (vovr != nullptr)
+                    rec_set_value<VT, RW>(reinterpret_cast<int *>(&sm.rec[e * RQ]), vovr[t0 + e]);
+                k = lds_sub<RW>(&sm.rec[e * RQ], n);
+            }
+            sm.key[e] = k;
+        }
+        __syncthreads();
+        // 2. sort the subscripts
+        tile_sort(sm);
+        // 3. segmented sums over this wavefront's quarter of the sorted tile
+        const int gb = wave * SM::WS + g * S;
+        const int ge = (gb + S < valid) ? gb + S : valid;
+        int key = -1, first_key = -1;
+        AT acc[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[c] = 0;
+        if (gl == 0) {
+            sm.pkey[wave][2 * g] = -1;
+            sm.pkey[wave][2 * g + 1] = -1;
+        }
+        for (int s0 = gb; s0 < ge; s0 += U) {
+            AT t[U][CPL];
+            int kk[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                kk[u] = -1;
+                if (s0 + u < ge) {
+                    const int q = sm.pos[s0 + u];
+                    int w[RW];
+                    lds_record<RQ>(&sm.rec[q * RQ], w);
+                    kk[u] = sm.key[s0 + u];
+                    entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (kk[u] < 0) continue;
+                if (kk[u] != key) {
+                    if (key >= 0) {
+                        if (key == first_key) {
+#pragma unroll
+                            for (int c = 0; c < CPL; ++c) sm.part[wave][2 * g][col0 + c] = acc[c];
+                            if (gl == 0) sm.pkey[wave][2 * g] = key;
+                        } else if (colok) {
+                            atomic_cols<AT, CPL>(V + (int64_t)key * R + col0, acc);
+                        }
+                    } else {
+                        first_key = kk[u];
+                    }
+                    key = kk[u];
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) acc[c] = 0;
+                }
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) acc[c] += t[u][c];
+            }
+        }
+        if (key >= 0) {
+            // the last row (also the first, when the slice holds one row: its first slot stays
+            // empty)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) sm.part[wave][2 * g + 1][col0 + c] = acc[c];
+            if (gl == 0) sm.pkey[wave][2 * g + 1] = key;
+        }
+        wave_sync();
+        // the groups' first and last rows, in sorted order: inner runs go to V, the wavefront's
+        // first and last rows to the workgroup
+        if (g == 0)
+            combine_runs<false, CPL, AT>(sm.part[wave], sm.pkey[wave], 2 * NG, col0, colok, gl, V,
+                                         R, sm.wpart[2 * wave], &sm.wkey[2 * wave],
+                                         sm.wpart[2 * wave + 1], &sm.wkey[2 * wave + 1]);
+        __syncthreads();
+        // 4. the wavefronts' first and last rows: one atomic per distinct row
+        if (wave == 0 && g == 0)
+            combine_runs<true, CPL, AT>(sm.wpart, sm.wkey, 2 * NW, col0, colok, gl, V, R, nullptr,
+                                        nullptr, nullptr, nullptr);
+        __syncthreads();
+    }
+}
+
+template <int D, int G, int CPL, class FT, class VT, class AT>
+__global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
+    const int4 *__restrict__ rec, int64_t P, int n, int R, FactorSet<FT> A,
+    const double *__restrict__ lambda, const VT *__restrict__ vovr, AT *__restrict__ V,
+    int64_t per_block) {
+    extern __shared__ int4 smem4[];
+    using SM = AtomicTileShared<D, G, CPL, VT, AT>;
+    const int64_t r0 = (int64_t)blockIdx.x * per_block;
+    const int64_t r1 = (r0 + per_block < P) ? r0 + per_block : P;
+    atomic_tile_range<D, G, CPL, FT, VT, AT>(*reinterpret_cast<SM *>(smem4), rec, n, R, A,
+                                             lambda, vovr, V, r0, r1);
+}
+
+// Privatised output for short modes (Sec. 8 proposes private result copies reduced afterwards,
+// a hybrid of the atomic and the reduction strategies): one LDS copy of the whole V per
+// workgroup, each product row added there with LDS atomics, and one flush of the non-zero
+// entries per workgroup.  The workgroup processes storage positions [bc0, bc0 + 4 chunk), one
+// chunk per wavefront.  Every thread of the workgroup must call it.
+template <int D, int G, int CPL, class FT, class VT, class AT>
+__device__ __forceinline__ void privatized_block_unit(int4 *smem4, const int4 *__restrict__ rec,
+                                                      int64_t P, int n, int R,
+                                                      const FactorSet<FT> &A,
+                                                      const double *__restrict__ lambda,
+                                                      const VT *__restrict__ vovr,
+                                                      AT *__restrict__ V, int chunk, int In,
+                                                      int64_t bc0) {
+    constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
+    constexpr int RP = G * CPL;
+    constexpr int U = UnrollFor<KERNEL_ATOMIC, G, CPL, FT>::value;
     int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
-    // hbits > 0: hash table of 2^hbits rows; hbits == 0: no table; hbits < 0: "privatised"
-    // output, one LDS row per output row k < In (slot = k, no keys)
-    const bool direct = hbits < 0;
-    int *hkeys = reinterpret_cast<int *>(smem4 + (kBlock / kWave) * kWave * RQ);
-    const int H = direct ? In : (hbits > 0 ? (1 << hbits) : 0);
-    AT *hvals = direct ? reinterpret_cast<AT *>(hkeys) : reinterpret_cast<AT *>(hkeys + (H > 2 ? H : 2));
+    AT *pvals = reinterpret_cast<AT *>(smem4 + (kBlock / kWave) * kWave * RQ);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane / G, gl = lane % G;
@@ -670,9 +942,7 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
     const uint32_t rowbytes = (uint32_t)R * sizeof(FT);
     const uint32_t colbytes = colok ? (uint32_t)col0 * sizeof(FT) : 0u;
     const OtherModes<D> om = other_modes<D>(A, n);
-    if (!direct)
-        for (int i = tid; i < H; i += kBlock) hkeys[i] = -1;
-    for (int i = tid; i < H * RP; i += kBlock) hvals[i] = 0;
+    for (int i = tid; i < In * RP; i += kBlock) pvals[i] = 0;
     __syncthreads();
 
     AT lam[CPL];
@@ -684,28 +954,6 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
     const int64_t c1 = (c0 + chunk < P) ? c0 + chunk : P;
     const int len = c1 > c0 ? (int)(c1 - c0) : 0;
     const int nb = (len + kWave - 1) / kWave;
-    if (!direct && H > 0) {
-        // heavy rows claim first: a row met at least twice among a wave's first 64 entries takes
-        // its slot before any other row can fill the table.  A row holding a large share of the
-        // entries then never falls back to direct adds of small terms into its large FP32 sum,
-        // which would round many of them away.
-        const int m = len < kWave ? len : kWave;
-        if (lane < m) {
-            s_rec[lane * RQ] = rec[(c0 + lane) * RQ];
-            if constexpr (RQ == 2) s_rec[lane * RQ + 1] = rec[(c0 + lane) * RQ + 1];
-        }
-        wave_sync();
-        const int k = lane < m ? lds_sub<RW>(&s_rec[lane * RQ], n) : -1;
-        int cnt = 0;
-        bool first = true;
-        for (int j = 0; j < m; ++j) {
-            const int kj = lds_sub<RW>(&s_rec[j * RQ], n);
-            cnt += (kj == k) ? 1 : 0;
-            if (kj == k && j < lane) first = false;
-        }
-        if (k >= 0 && cnt >= 2 && first) (void)table_slot(hkeys, H, hbits, k);
-        __syncthreads();
-    }
     for (int b = 0; b < nb; ++b) {
         const int off = b * kWave + lane;
         if (off < len) {
@@ -721,66 +969,42 @@ __device__ __forceinline__ void atomic_block_unit(int4 *smem4, const int4 *__res
         for (int s0 = 0; s0 < cnt; s0 += U) {
             AT t[U][CPL];
             int kk[U];
-            if (s0 + U <= cnt) {  // whole unroll: straight-line code, all gathers in flight
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < U; ++u) {
+                const int s = s0 + u;
+                kk[u] = -1;
+                if (s < cnt) {
                     int w[RW];
-                    lds_record<RQ>(&s_rec[(g * G + s0 + u) * RQ], w);
-                    kk[u] = lds_sub<RW>(&s_rec[(g * G + s0 + u) * RQ], n);
+                    lds_record<RQ>(&s_rec[(g * G + s) * RQ], w);
+                    kk[u] = lds_sub<RW>(&s_rec[(g * G + s) * RQ], n);
                     entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int s = s0 + u;
-                    kk[u] = -1;
-                    if (s < cnt) {
-                        int w[RW];
-                        lds_record<RQ>(&s_rec[(g * G + s) * RQ], w);
-                        kk[u] = lds_sub<RW>(&s_rec[(g * G + s) * RQ], n);
-                        entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
-                    }
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int k = kk[u];
-                if (k < 0) continue;
-                int slot = direct ? k : -1;
-                if (!direct && H > 0) slot = table_slot(hkeys, H, hbits, k);
-                if (colok) {
-                    if (slot >= 0) {
+                if (kk[u] < 0 || !colok) continue;
 #pragma unroll
-                        for (int c = 0; c < CPL; ++c) atomicAdd(&hvals[slot * RP + col0 + c], t[u][c]);
-                    } else {
-                        atomic_cols<AT, CPL>(V + (int64_t)k * R + col0, t[u]);
-                    }
-                }
+                for (int c = 0; c < CPL; ++c) atomicAdd(&pvals[kk[u] * RP + col0 + c], t[u][c]);
             }
         }
         wave_sync();
     }
     __syncthreads();
-    for (int i = tid; i < H * RP; i += kBlock) {
-        const int slot = i / RP, col = i - slot * RP;
-        if (direct) {
-            // skip untouched entries: adding zero changes nothing
-            if (col < R && hvals[i] != (AT)0) atomic_add_f(V + (int64_t)slot * R + col, hvals[i]);
-        } else {
-            const int k = hkeys[slot];
-            if (k >= 0 && col < R) atomic_add_f(V + (int64_t)k * R + col, hvals[i]);
-        }
+    // skip untouched entries: adding zero changes nothing
+    for (int i = tid; i < In * RP; i += kBlock) {
+        const int row = i / RP, col = i - row * RP;
+        if (col < R && pvals[i] != (AT)0) atomic_add_f(V + (int64_t)row * R + col, pvals[i]);
     }
 }
 
 template <int D, int G, int CPL, class FT, class VT, class AT>
-__global__ __launch_bounds__(kBlock) void k_mttkrp_atomic(
+__global__ __launch_bounds__(kBlock) void k_mttkrp_privatized(
     const int4 *__restrict__ rec, int64_t P, int n, int R, FactorSet<FT> A,
     const double *__restrict__ lambda, const VT *__restrict__ vovr, AT *__restrict__ V,
-    int chunk, int hbits, int In) {
+    int chunk, int In) {
     extern __shared__ int4 smem4[];
-    atomic_block_unit<D, G, CPL, FT, VT, AT>(smem4, rec, P, n, R, A, lambda, vovr, V, chunk, hbits, In,
-                                             (int64_t)blockIdx.x * (kBlock / kWave) * chunk);
+    privatized_block_unit<D, G, CPL, FT, VT, AT>(smem4, rec, P, n, R, A, lambda, vovr, V, chunk, In,
+                                                 (int64_t)blockIdx.x * (kBlock / kWave) * chunk);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -800,11 +1024,11 @@ struct MttkrpArgs {
     const void *vovr;
     void *V;
     int chunk;
-    int hbits;
+    int privatized;   // atomic algorithm into a per-workgroup LDS copy of the whole output
     int algo;
     int *slot_keys;   // deterministic mode: 2 slots per wave chunk (null: boundary atomics)
     void *slot_vals;
-    int In;           // output rows (privatised mode: hbits < 0)
+    int In;           // output rows (privatised mode)
     int auto_chunk;   // chunk is the default and may be matched to the resident capacity
     int cus;          // compute units of the device
     int *query_chunk; // non-null: store the chunk the launch would use, launch nothing
@@ -826,12 +1050,6 @@ inline int capacity_chunk(int64_t P, int64_t cap, int dflt) {
         if (c <= 32768) return c >= 8192 ? (int)c : dflt;
     }
     return dflt;
-}
-
-template <class AT>
-inline size_t atomic_smem_bytes(int RQ, int H, int RP) {
-    return (size_t)(kBlock / kWave) * kWave * RQ * 16 + (size_t)(H > 2 ? H : 2) * 4 +
-           (size_t)H * RP * sizeof(AT);
 }
 
 template <class AT>
@@ -873,17 +1091,27 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
                                dim3(kBlock), 0, a.stream, a.slot_keys,
                                static_cast<const AT *>(a.slot_vals), nslots, a.R, V);
         }
+    } else if (a.privatized) {
+        if (a.query_chunk != nullptr) {
+            *a.query_chunk = a.chunk;
+            return SPT_OK;
+        }
+        const size_t smem = privatized_smem_bytes<AT>(RecShape<D, VT>::RQ, a.In, G * CPL);
+        hipLaunchKernelGGL((k_mttkrp_privatized<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock),
+                           smem, a.stream, a.rec, a.P, a.n, a.R, A, a.lambda, vovr, V, a.chunk,
+                           a.In);
     } else {
         if (a.query_chunk != nullptr) {
             *a.query_chunk = a.chunk;
             return SPT_OK;
         }
-        const int H = a.hbits > 0 ? (1 << a.hbits) : 0;
-        const size_t smem = a.hbits < 0 ? privatized_smem_bytes<AT>(RecShape<D, VT>::RQ, a.In, G * CPL)
-                                        : atomic_smem_bytes<AT>(RecShape<D, VT>::RQ, H, G * CPL);
-        hipLaunchKernelGGL((k_mttkrp_atomic<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock),
-                           smem, a.stream, a.rec, a.P, a.n, a.R, A, a.lambda, vovr, V, a.chunk,
-                           a.hbits, a.In);
+        // a workgroup takes four wave chunks of entries, rounded up to whole sorted tiles
+        constexpr int T = AtomicTileShared<D, G, CPL, VT, AT>::T;
+        const int64_t per_block = ceil_div((int64_t)a.chunk * (kBlock / kWave), T) * T;
+        const unsigned agrid = (unsigned)ceil_div(a.P, per_block);
+        const size_t smem = atomic_tile_smem_bytes<D, G, CPL, VT, AT>();
+        hipLaunchKernelGGL((k_mttkrp_atomic<D, G, CPL, FT, VT, AT>), dim3(agrid), dim3(kBlock),
+                           smem, a.stream, a.rec, a.P, a.n, a.R, A, a.lambda, vovr, V, per_block);
     }
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }

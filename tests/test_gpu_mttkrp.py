@@ -456,33 +456,43 @@ def test_privatized_short_mode(gpu):
         assert e.value.code == -6
 
 
-def test_atomic_table_budget(gpu):
-    """Atomic kernel with explicit LDS budgets for its combining table (from a 2-slot table at
-    1 KiB to 64 KiB, FP32 and FP64): parity with the oracle; budgets beyond 64 KiB rejected."""
+@pytest.mark.parametrize("kind", ["f32", "f64"])
+def test_atomic_sorted_tile_edges(gpu, kind):
+    """The atomic kernel sorts tiles of entries by output row: entry counts around the tile size
+    (a single entry, one short tile, exactly one tile, one entry past it, several tiles and a
+    tail), a tensor whose entries all share one output row (one run across every lane group,
+    wavefront and tile), every output row distinct, layouts with several columns per lane and
+    short and long workgroup ranges, against the oracle.  FP64 values take 32-byte records
+    (smaller tiles)."""
     import paper_1809_09175_amd as spt
-    from paper_1809_09175_amd import SptError
-    dims = (900, 70, 3000)
-    for kind, dtype in (("f32", np.float32), ("f64", np.float64)):
-        X = _small(kind, dims, 70_001, (1.3, 1.1, 0.0), seed=31)
-        T = _dev_tensor(X, dtype)
-        for R in (8, 32):
-            dev, ref = _factors(dims, R, seed=R + 1, kind=kind)
-            for kib in (0, 1, 8, 16, 48, 64):
+    dims = (6000, 50, 40)
+    dtype = np.float64 if kind == "f64" else np.float32
+    for P in (1, 511, 1024, 1025, 4097):
+        for pattern in ("one_row", "distinct", "skewed"):
+            X = _small(kind, dims, P, (1.2, 0.0, 0.0), seed=P)
+            if pattern == "one_row":
+                X.subs[:, 0] = 7
+            elif pattern == "distinct":
+                X.subs[:, 0] = np.random.default_rng(P).permutation(dims[0])[:P]
+            T = _dev_tensor(X, dtype)
+            for R, lanes, cols, chunk in ((8, 0, 0, 0), (32, 8, 4, 64), (16, 16, 1, 1024),
+                                          (24, 8, 4, 4096)):
+                if R % max(cols, 1):
+                    continue
+                dev, ref = _factors(dims, R, seed=R, kind=kind)
                 for n in range(3):
-                    _log(f"table budget kind={kind} R={R} kib={kib} mode={n}")
-                    V = spt.mttkrp(T, dev, n, algo="atomic", lds_kib=kib)
+                    _log(f"atomic tiles {kind} P={P} {pattern} R={R} {lanes}x{cols} chunk={chunk} n={n}")
+                    V = spt.mttkrp(T, dev, n, algo="atomic", lanes=lanes, cols=cols, chunk=chunk)
                     torch.cuda.synchronize()
                     assert _relerr(V.cpu().numpy(),
-                                   oracle.mttkrp(X.subs, X.vals, dims, ref, n)) < TOL[kind]
-        with pytest.raises(SptError) as e:
-            spt.mttkrp(T, dev, 0, algo="atomic", lds_kib=65)
-        assert e.value.code == -1
+                                   oracle.mttkrp(X.subs, X.vals, dims, ref, n)) < TOL[kind], \
+                        (P, pattern, R, lanes, cols, chunk, n)
 
 
 def test_atomic_heavy_row_accuracy(gpu):
     """Rows holding a large share of the entries (Zipf exponent 1.1 over 200000 rows, the
-    hottest about a tenth of 8e6 entries) with a combining table far smaller than the distinct
-    rows one workgroup meets: the heavy rows' FP32 sums stay within the FP32 tolerance."""
+    hottest about a tenth of 8e6 entries), in several lane layouts: the heavy rows' FP32 sums
+    (one pre-summed term per sorted tile) stay within the FP32 tolerance."""
     import paper_1809_09175_amd as spt
     dims = (200_000, 3000, 5000)
     X = datagen.skewed_tensor(dims, 8_000_000, (1.1, 0.0, 0.0), seed=41)
@@ -496,10 +506,10 @@ def test_atomic_heavy_row_accuracy(gpu):
     s, v = _sampled_rows(X, 0, rows)
     V_ref = oracle.mttkrp(s, v, dims, ref, 0)[rows]
     hot = rows == heavy[-1]
-    for kib in (0, 8, 16):
-        _log(f"heavy rows kib={kib}")
-        V = spt.mttkrp(T, dev, 0, algo="atomic", lds_kib=kib)
+    for lanes, cols in ((0, 0), (8, 4), (16, 2)):
+        _log(f"heavy rows {lanes}x{cols}")
+        V = spt.mttkrp(T, dev, 0, algo="atomic", lanes=lanes, cols=cols)
         torch.cuda.synchronize()
         got = V[torch.from_numpy(rows).cuda()].cpu().numpy()
-        assert _relerr(got[hot], V_ref[hot]) < TOL["f32"], kib
-        assert _relerr(got, V_ref) < TOL["f32"], kib
+        assert _relerr(got[hot], V_ref[hot]) < TOL["f32"], (lanes, cols)
+        assert _relerr(got, V_ref) < TOL["f32"], (lanes, cols)
