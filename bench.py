@@ -45,24 +45,52 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_counters(kernel_name):
-    """HBM traffic per dispatch of the dominant kernel, from the committed rocprofv3 counter
-    summary; None when absent, taken for another kernel instantiation, or taken from a
-    different kernel source."""
-    path = os.path.join(ROOT, "profiles", "mttkrp_perm_powerlaw3_R32_counters.txt")
-    if not os.path.exists(path):
-        return None
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "mttkrp_powerlaw3_R32_counters.txt")
+
+
+def read_counters():
+    """HBM traffic per dispatch of the MTTKRP kernels, from the committed rocprofv3 counter
+    summary: {variant: {"kernel": name, "grid": workgroups, "bytes": calibrated bytes}}.  Empty
+    when absent or taken from a different kernel source."""
+    if not os.path.exists(COUNTERS_FILE):
+        return {}
     kv = {}
-    for line in open(path):
+    for line in open(COUNTERS_FILE):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash() or kv.get("kernel") != kernel_name:
-        return None
-    try:
-        return float(kv["hbm_bytes_per_dispatch"])
-    except (KeyError, ValueError):
-        return None
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return {}
+    out = {}
+    for k, v in kv.items():
+        if "." not in k:
+            continue
+        var, field = k.split(".", 1)
+        out.setdefault(var, {})[field] = v
+    res = {}
+    for var, f in out.items():
+        try:
+            res[var] = {"kernel": f["kernel"], "grid": int(f["grid"]),
+                        "bytes": float(f["hbm_bytes_per_dispatch"])}
+        except (KeyError, ValueError):
+            continue
+    return res
+
+
+def touched_rows(X):
+    """Rows of each mode that hold at least one entry."""
+    return [int(np.count_nonzero(np.bincount(X.subs[:, m], minlength=X.dims[m])))
+            for m in range(X.d)]
+
+
+def compulsory_bytes(touched, n, R, rec_bytes, s_f, s_out, extra_per_entry, P):
+    """Unique bytes one mode-n MTTKRP must move: every record once (plus per-entry index
+    arrays the traversal reads, e.g. the permutation), every touched row of the other factor
+    matrices once, and every touched row of V written once."""
+    b = P * (rec_bytes + extra_per_entry)
+    for m, t in enumerate(touched):
+        b += t * R * (s_out if m == n else s_f)
+    return b
 
 
 def _rows_fp64(subs, vals, factors, n, rows, chunk=1 << 20):
@@ -279,6 +307,143 @@ def bench_gcp(spt, datagen, torch, dev, R=32, steps=3):
     return res
 
 
+# ------------------------------------------------------------------------------------------
+# rocprofv3 summaries (python3 bench.py --summarize-profile DIR): DIR holds prof_trace/ (a
+# --kernel-trace --stats run of bench.py --profile) and, optionally, prof_fetch/ and prof_write/
+# (--pmc FETCH_SIZE and --pmc WRITE_SIZE runs of the same command)
+# ------------------------------------------------------------------------------------------
+
+PROFILE_CMD = ("cd /tmp && export TMPDIR=/tmp && R=<repository root>; "
+               "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/pc/prof_trace -o run -- "
+               "python3 $R/bench.py --profile; then, each in a run of its own: "
+               "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/pc/prof_fetch -o run -- "
+               "python3 $R/bench.py --profile; "
+               "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/pc/prof_write -o run -- "
+               "python3 $R/bench.py --profile; then, from the repository root: "
+               "python3 bench.py --summarize-profile gpurun_out/pc")
+TRIAD_READ_BYTES = 2 * (1 << 28) * 4   # the --profile triad reads b and c (2^28 floats each)
+TRIAD_WRITE_BYTES = (1 << 28) * 4      # and writes a
+
+
+def _short_kernel(name):
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    depth, out = 0, []
+    for ch in name:  # drop the argument list, keep the template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out)
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(dirpath, suffix):
+    for root, _, files in os.walk(dirpath):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    return None
+
+
+def _profile_variants(groups):
+    """Benchmark leg of each (kernel, grid) group, from the order --profile runs them in: the
+    first FP32 permuted-kernel group is the sorted-copy leg, the second the gather leg."""
+    legs = {}
+    perm32 = [k for k in sorted(groups, key=lambda k: groups[k]["first"])
+              if k[0].startswith("spt::k_mttkrp_perm<3,") and k[0].endswith("float, float, float>")]
+    if perm32:
+        legs[perm32[0]] = "copy"
+    if len(perm32) > 1:
+        legs[perm32[1]] = "gather"
+    for k in groups:
+        if k[0].startswith("spt::k_mttkrp_atomic<3,") and k[0].endswith("float, float, float>"):
+            legs[k] = "atomic"
+        if k[0].startswith("spt::k_mttkrp_perm<3,") and k[0].endswith("double, double, double>"):
+            legs[k] = "copy_f64"
+    return legs
+
+
+def summarize_profile(dirpath):
+    """Markdown summary and counter file text of a profiled --profile run."""
+    trace = _read_csv(_find(os.path.join(dirpath, "prof_trace"), "kernel_trace.csv"))
+    groups = {}
+    for r in trace:
+        key = (_short_kernel(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) *
+               int(r["Grid_Size_Z"]))
+        g = groups.setdefault(key, {"dur": [], "first": int(r["Dispatch_Id"])})
+        g["dur"].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+    total = sum(sum(g["dur"]) for g in groups.values())
+    legs = _profile_variants(groups)
+    lines = ["# rocprofv3 summary: MTTKRP kernels on powerlaw3 (1e8 entries), R = 32", "",
+             "Command (run from the repository root on the GPU box):", "", "```", PROFILE_CMD,
+             "```", "",
+             "The profiled run (`bench.py --profile`) times each R = 32 leg after its own warm-up "
+             "launches: sorted copies (3 warm-up + 5 timed steps of three modes), gather (2 + 2), "
+             "atomic (2 + 2), FP64 sorted copies (3 + 2), then one triad (the counter "
+             "calibration kernel). Durations in microseconds per dispatch; grid in work-items.",
+             "", "| kernel | leg | grid | calls | median | mean | min | max | % time |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    for key in sorted(groups, key=lambda k: -sum(groups[k]["dur"])):
+        d = np.array(groups[key]["dur"])
+        lines.append(f"| `{key[0]}` | {legs.get(key, '')} | {key[1]} | {len(d)} | "
+                     f"{np.median(d):.1f} | {d.mean():.1f} | {d.min():.1f} | {d.max():.1f} | "
+                     f"{100 * d.sum() / total:.2f} |")
+    counters_txt = None
+    fpath = _find(os.path.join(dirpath, "prof_fetch"), "counter_collection.csv")
+    wpath = _find(os.path.join(dirpath, "prof_write"), "counter_collection.csv")
+    if fpath and wpath:
+        vals = {}
+        for name, path in (("FETCH_SIZE", fpath), ("WRITE_SIZE", wpath)):
+            for r in _read_csv(path):
+                if r["Counter_Name"] != name:
+                    continue
+                key = (_short_kernel(r["Kernel_Name"]), int(r["Grid_Size"]))
+                vals.setdefault(key, {}).setdefault(name, []).append(float(r["Counter_Value"]))
+        tri = [k for k in vals if k[0] == "spt::k_triad"]
+        if not tri:
+            raise SystemExit("no triad dispatch in the counter runs: cannot calibrate")
+        ff = TRIAD_READ_BYTES / 1024 / np.mean(vals[tri[0]]["FETCH_SIZE"])
+        wf = TRIAD_WRITE_BYTES / 1024 / np.mean(vals[tri[0]]["WRITE_SIZE"])
+        lines += ["", "## HBM traffic per dispatch (FETCH_SIZE, then WRITE_SIZE, separate runs)",
+                  "", f"Calibration: the triad reads {TRIAD_READ_BYTES} and writes "
+                  f"{TRIAD_WRITE_BYTES} bytes; FETCH_SIZE reports "
+                  f"{np.mean(vals[tri[0]]['FETCH_SIZE']):.0f} KiB (bytes = KiB x 1024 x "
+                  f"{ff:.4f}), WRITE_SIZE {np.mean(vals[tri[0]]['WRITE_SIZE']):.0f} KiB "
+                  f"(x {wf:.4f}).", "",
+                  "| kernel | leg | grid | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | "
+                  "GB read | GB written |", "|---|---|---|---|---|---|---|---|"]
+        clines = ["# HBM bytes per dispatch of the MTTKRP legs of bench.py --profile "
+                  "(powerlaw3, 1e8 entries, R = 32), calibrated rocprofv3 FETCH_SIZE + WRITE_SIZE",
+                  "# command: " + PROFILE_CMD,
+                  f"# calibration from the triad: fetch x{ff:.4f}, write x{wf:.4f}",
+                  f"kernel_source_hash = {kernel_source_hash()}"]
+        ctr_legs = _profile_variants({k: {"first": min(groups.get(k, {"first": 1 << 62})["first"],
+                                                       1 << 62)} for k in vals})
+        for key in sorted(vals, key=lambda k: -np.mean(vals[k].get("FETCH_SIZE", [0]))):
+            fk = np.mean(vals[key].get("FETCH_SIZE", [np.nan]))
+            wk = np.mean(vals[key].get("WRITE_SIZE", [np.nan]))
+            rb, wb = fk * 1024 * ff, wk * 1024 * wf
+            leg = ctr_legs.get(key, "")
+            lines.append(f"| `{key[0]}` | {leg} | {key[1]} | "
+                         f"{len(vals[key].get('FETCH_SIZE', []))} | {fk:.0f} | {wk:.0f} | "
+                         f"{rb / 1e9:.3f} | {wb / 1e9:.3f} |")
+            if leg:
+                clines += [f"{leg}.kernel = {key[0]}", f"{leg}.grid = {key[1]}",
+                           f"{leg}.fetch_kib_per_dispatch = {fk:.1f}",
+                           f"{leg}.write_kib_per_dispatch = {wk:.1f}",
+                           f"{leg}.hbm_bytes_per_dispatch = {rb + wb:.0f}"]
+        counters_txt = "\n".join(clines) + "\n"
+    return "\n".join(lines) + "\n", counters_txt
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,14 +452,23 @@ def main():
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--quick", action="store_true", help="skip the extra workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="write the rocprofv3 summaries of a profiled --profile run (DIR holds "
+                         "prof_trace/, prof_fetch/, prof_write/) into profiles/ and exit")
     ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: R=32 permuted (sorted copies) and atomic, 2 "
-                         "steps each, plus one triad over 3 x 1 GiB (the counter calibration "
-                         "kernel)")
-    ap.add_argument("--profile-gather", action="store_true",
-                    help="as --profile, with the permuted kernel gathering records through the "
-                         "permutation instead of reading the sorted copies")
+                    help="short run for rocprofv3: the R=32 legs only (sorted copies 3 warm-up "
+                         "+ 5 timed steps, gather, atomic, FP64 sorted copies), plus one triad "
+                         "over 3 x 1 GiB (the counter calibration kernel)")
     args = ap.parse_args()
+    if args.summarize_profile:
+        md, ctr = summarize_profile(args.summarize_profile)
+        with open(os.path.join(ROOT, "profiles", "mttkrp_powerlaw3_R32.md"), "w") as fh:
+            fh.write(md)
+        if ctr is not None:
+            with open(COUNTERS_FILE, "w") as fh:
+                fh.write(ctr)
+        print(md)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -386,15 +560,13 @@ def main():
                 "wall_s": wall}
 
     R = args.rank
-    if args.profile_gather:
-        args.profile = True
     # mode-sorted record copies: built once, like the permutations
     T.sort_copy()
     torch.cuda.synchronize()
     copy_ms = timed(lambda: T.sort_copy())
     log(f"sorted record copies, all modes: {copy_ms:.2f} ms")
     if args.profile:
-        args.steps, args.warmup, args.quick, args.no_cpu = 2, 1, True, True
+        args.steps, args.warmup, args.quick, args.no_cpu = 5, 3, True, True
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device=dev)
         b = torch.rand(n, dtype=torch.float32, device=dev)
@@ -402,13 +574,46 @@ def main():
         spt.stream_triad(a, b, c)
         torch.cuda.synchronize()
         del a, b, c
-    main_res = measure(R, "permuted" if args.profile_gather else "permuted_copy", args.steps,
-                       args.warmup)
+    main_res = measure(R, "permuted_copy", args.steps, args.warmup)
     log(f"R={R} permuted (sorted copies): {main_res['ms_per_step']:.3f} ms/step, {main_res['gbs']:.0f} GB/s")
-    gather_res = main_res if args.profile else measure(R, "permuted", max(2, args.steps // 2), 2)
+    gather_res = measure(R, "permuted", max(2, args.steps // 2), min(args.warmup, 2))
     log(f"R={R} permuted (gather): {gather_res['ms_per_step']:.3f} ms/step, {gather_res['gbs']:.0f} GB/s")
-    atomic_res = measure(R, "atomic", max(2, args.steps // 2), 1 if args.profile else 2)
+    atomic_res = measure(R, "atomic", max(2, args.steps // 2), 2)
     log(f"R={R} atomic:   {atomic_res['ms_per_step']:.3f} ms/step, {atomic_res['gbs']:.0f} GB/s")
+    touched = touched_rows(X)
+    # the paper's arithmetic (Sec. 7: FP64 values and factors): the same tensor with FP64
+    # values (32-byte records), FP64 factors and V, sorted copies, all modes
+    T64 = spt.SparseTensor(torch.from_numpy(X.subs).to(dev),
+                           torch.from_numpy(X.vals.astype(np.float64)).to(dev), X.dims)
+    T64.validate()
+    T64.permute()
+    T64.sort_copy()
+    A64 = factors_for(R, np.float64)
+    outs64 = [torch.empty((I, R), dtype=torch.float64, device=dev) for I in X.dims]
+    for _ in range(args.warmup):
+        for n in range(d):
+            spt.mttkrp(T64, A64, n, out=outs64[n])
+    ev64 = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in range(d)]
+    f64_mode_ms = np.zeros(d)
+    f64_steps = max(2, args.steps // 2)
+    torch.cuda.synchronize()
+    for _ in range(f64_steps):
+        for n in range(d):
+            ev64[n][0].record(stream)
+            spt.mttkrp(T64, A64, n, out=outs64[n])
+            ev64[n][1].record(stream)
+        torch.cuda.synchronize()
+        f64_mode_ms += [ev64[n][0].elapsed_time(ev64[n][1]) for n in range(d)]
+    f64_mode_ms /= f64_steps
+    f64_ms = float(f64_mode_ms.sum())
+    f64_model = P * model_bytes(d, R, s_val=8, s_f=8, s_out=8) * d
+    f64_res = {"ms_per_step": round(f64_ms, 3),
+               "model_gbs": round(f64_model / (f64_ms * 1e-3) / 1e9, 1),
+               "per_mode_ms": [round(x, 4) for x in f64_mode_ms]}
+    log(f"R={R} FP64 permuted (sorted copies): {f64_ms:.3f} ms/step")
+    del T64, A64, outs64
+    torch.cuda.empty_cache()
 
     extras = {}
     per_rank = {}
@@ -487,25 +692,56 @@ def main():
         extras["batch64"] = bench_batch64(spt, datagen, torch, dev)
         extras["gcp_poisson"] = bench_gcp(spt, datagen, torch, dev)
 
-    # roofline of the dominant kernel (the permuted MTTKRP); per launch = one mode
+    # roofline of the dominant kernel (the permuted MTTKRP over sorted copies) and of the other
+    # two traversals; per launch = one mode.  Three byte counts per launch: the paper's model
+    # (the metric; factor rows counted at every use, so it exceeds the HBM peak when they hit in
+    # cache), the HBM bytes rocprofv3's counters saw (calibrated), and the compulsory bytes.
+    counters = read_counters()
     dtune = spt.default_tune(T, 0, R, torch.float32, algo="permuted_copy")
-    avg_launch_ms = float(np.mean(main_res["per_mode_ms"]))
-    per_launch_bytes = P * model_bytes(d, R)
-    achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
     kname = f"spt::k_mttkrp_perm<3, {dtune['lanes']}, {dtune['cols']}, float, float, float>"
-    traffic = read_counters(kname)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic,
+
+    def kernel_roofline(variant, res, rec_bytes, extra, s_val=4, s_f=4, s_out=4):
+        avg_ms = float(np.mean(res["per_mode_ms"]))
+        model = P * model_bytes(d, R, s_val=s_val, s_f=s_f, s_out=s_out)
+        comp = float(np.mean([compulsory_bytes(touched, n, R, rec_bytes, s_f, s_out, extra, P)
+                              for n in range(d)]))
+        c = counters.get(variant)
+        r = {"avg_launch_ms": round(avg_ms, 4),
+             "model_bytes": model, "model_gbs": round(model / (avg_ms * 1e-3) / 1e9, 1),
+             "compulsory_bytes": round(comp),
+             "compulsory_gbs": round(comp / (avg_ms * 1e-3) / 1e9, 1),
+             "compulsory_frac": round(comp / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "counter_bytes": None, "counter_gbs": None, "counter_frac": None,
+             "counter_over_compulsory": None}
+        if c is not None:
+            r["kernel"] = c["kernel"]
+            r["counter_bytes"] = c["bytes"]
+            r["counter_gbs"] = round(c["bytes"] / (avg_ms * 1e-3) / 1e9, 1)
+            r["counter_frac"] = round(c["bytes"] / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            r["counter_over_compulsory"] = round(c["bytes"] / comp, 3)
+        return r
+
+    kr = {"permuted_copy": kernel_roofline("copy", main_res, 16, 0),
+          "permuted_gather": kernel_roofline("gather", gather_res, 16, 4),
+          "atomic": kernel_roofline("atomic", atomic_res, 16, 0),
+          "permuted_copy_f64": kernel_roofline("copy_f64", f64_res, 32, 0, 8, 8, 8)}
+    dom = kr["permuted_copy"]
+    have = dom["counter_bytes"] is not None
+    # achieved = HBM bytes per launch (calibrated counters) over the live average launch time;
+    # without current counters, the compulsory bytes (a lower bound) stand in and say so
+    achieved = dom["counter_gbs"] if have else dom["compulsory_gbs"]
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": dom["counter_bytes"],
+                "bytes_basis": "rocprofv3 FETCH_SIZE/WRITE_SIZE per launch, calibrated" if have
+                               else "compulsory bytes (counters absent for this kernel source)",
                 "kernel": kname + " reading the sorted record copies",
-                "per_launch_model_bytes": per_launch_bytes,
-                "avg_launch_ms": round(avg_launch_ms, 4)}
-    if traffic is not None:
-        # the HBM bytes the counters saw per launch over the same launch time: the physical
-        # share of the HBM peak (model bytes above exceed it because factor rows hit in cache)
-        phys = traffic / (avg_launch_ms * 1e-3) / 1e9
-        roofline["physical_gbs"] = round(phys, 1)
-        roofline["physical_frac"] = round(phys / HBM_PEAK_GBS, 4)
+                "avg_launch_ms": dom["avg_launch_ms"],
+                "model_bytes_per_launch": dom["model_bytes"], "model_gbs": dom["model_gbs"],
+                "compulsory_bytes_per_launch": dom["compulsory_bytes"],
+                "compulsory_frac": dom["compulsory_frac"],
+                "traffic_over_compulsory": dom["counter_over_compulsory"],
+                "kernels": kr}
 
     cpu = None
     if not args.no_cpu:
@@ -559,6 +795,8 @@ def main():
                    "permuted_speedup": round(atomic_res["ms_per_step"] / main_res["ms_per_step"], 3),
                    "permuted_gather_speedup": round(atomic_res["ms_per_step"] / gather_res["ms_per_step"], 3)},
         "per_mode_ms": [round(x, 4) for x in main_res["per_mode_ms"]],
+        "fp64": dict(f64_res, note="FP64 values (32-byte records), factors and V, as in the "
+                                   "paper's experiments; permuted traversal over sorted copies"),
         "per_rank": per_rank,
         "extras": extras,
         "roofline": roofline,
