@@ -203,11 +203,13 @@ int spt_mttkrp_default_tune(const spt_tensor *X, int mode, int R, int fdtype, in
  * vector size, columns per lane = block size / vector size) whenever that layout is compiled. */
 int spt_paper_block_sizes(int R, int *vector_size, int *fbs);
 
-/* Autotuner: times every compiled launch configuration for (X, mode, R, fdtype) on `stream`
- * (algorithm x lanes per entry x columns per lane x entries per wave; layouts that cover R with
- * at most twice R lanes-columns) and returns the fastest in *best and its time per launch in
- * *best_ms (host).  V is device scratch of the MTTKRP output size (overwritten).  reps: timed
- * launches per candidate (0 = 3).  Synchronises `stream`. */
+/* Autotuner: times the library's default configuration (spt_mttkrp_default_tune, with the
+ * chunk its launch uses) and every compiled launch configuration for (X, mode, R, fdtype) on
+ * `stream` (algorithm x lanes per entry x columns per lane x entries per wave; layouts that
+ * cover R with at most twice R lanes-columns), and returns the fastest in *best and its time
+ * per launch in *best_ms (host).  Each candidate runs once untimed, then `reps` launches timed
+ * one by one; its time is their median.  V is device scratch of the MTTKRP output size
+ * (overwritten).  reps: 0 = 7, at most 64.  Synchronises `stream`. */
 enum {
     SPT_TUNE_BATCH_CONFIGS = 1, /* only configurations the batched kernel supports */
     SPT_TUNE_NO_ATOMIC = 2,

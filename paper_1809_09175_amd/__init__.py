@@ -523,9 +523,10 @@ def gcp_sgd(X: SparseTensor, factors, loss="poisson", iters=100, samples=(1 << 1
 # ------------------------------------------------------------------ autotuner and batching
 
 def autotune(X: SparseTensor, factors, mode: int, batch=False, algos=("atomic", "permuted"),
-             reps=3, out=None, stream=None):
-    """Time every compiled launch configuration of this MTTKRP on the device; returns the
-    fastest as a dict(algo, lanes, cols, chunk, ms)."""
+             reps=0, out=None, stream=None):
+    """Time the library default and every compiled launch configuration of this MTTKRP on the
+    device (median of `reps` single launches each; 0 = the library's default count); returns
+    the fastest as a dict(algo, lanes, cols, chunk, ms)."""
     lib = _lib.load()
     ref = factors[0] if factors[0] is not None else factors[1]
     R = int(ref.shape[1])

@@ -1,5 +1,7 @@
 // Public MTTKRP entry point: argument checks, launch-parameter choice, output zeroing and
 // dispatch to the per-dtype kernel instantiations.
+#include <algorithm>
+
 #include "mttkrp_kernels.h"
 
 namespace spt {
@@ -323,29 +325,82 @@ extern "C" int spt_paper_block_sizes(int R, int *vector_size, int *fbs) {
     return SPT_OK;
 }
 
+constexpr int kTuneDefaultReps = 7;
+constexpr int kTuneMaxReps = 64;
+
+// Median time of `reps` individually timed launches of configuration r (after one untimed
+// launch): single launches of a small MTTKRP last microseconds, so one slow launch (a cold
+// cache, a clock step) must not decide the choice.
+static int time_config(const spt_tensor *X, int mode, int R, const void *const *factors,
+                       int fdtype, void *V, const spt_tune &r, int reps, hipEvent_t *ev,
+                       hipStream_t s, float *ms_out) {
+    int rc = launch_mttkrp(X, mode, R, factors, fdtype, nullptr, nullptr, V, r, s);
+    if (rc) return rc;
+    float t[kTuneMaxReps];
+    for (int k = 0; k < reps; ++k) {
+        if (hipEventRecord(ev[2 * k], s) != hipSuccess) return SPT_EHIP;
+        rc = launch_mttkrp(X, mode, R, factors, fdtype, nullptr, nullptr, V, r, s);
+        if (rc) return rc;
+        if (hipEventRecord(ev[2 * k + 1], s) != hipSuccess) return SPT_EHIP;
+    }
+    if (hipEventSynchronize(ev[2 * reps - 1]) != hipSuccess) return SPT_EHIP;
+    for (int k = 0; k < reps; ++k)
+        if (hipEventElapsedTime(&t[k], ev[2 * k], ev[2 * k + 1]) != hipSuccess) return SPT_EHIP;
+    std::sort(t, t + reps);
+    *ms_out = (reps % 2) ? t[reps / 2] : 0.5f * (t[reps / 2 - 1] + t[reps / 2]);
+    return SPT_OK;
+}
+
 extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
                                    const void *const *factors, int fdtype, void *V, int flags,
                                    int reps, spt_tune *best, float *best_ms, void *stream) {
     int rc = check_mttkrp_args(X, mode, R, factors, fdtype, V);
     if (rc) return rc;
     if (best == nullptr) return SPT_EINVAL;
-    if (reps < 1) reps = 3;
+    if (reps < 1) reps = kTuneDefaultReps;
+    if (reps > kTuneMaxReps) reps = kTuneMaxReps;
     hipStream_t s = static_cast<hipStream_t>(stream);
     static const int cfgs[][2] = {{4, 4},  {4, 8},  {8, 1},  {8, 2},  {8, 4},
                                   {8, 8},  {16, 1}, {16, 2}, {16, 4}, {16, 8},
                                   {32, 1}, {32, 2}, {64, 1}, {64, 2}, {64, 4}};
     static const int chunks[] = {512, 1024, 2048, 4096};
     const bool batch_only = (flags & SPT_TUNE_BATCH_CONFIGS) != 0;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return SPT_EHIP;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+    hipEvent_t ev[2 * kTuneMaxReps];
+    int nev = 0;
+    for (; nev < 2 * reps; ++nev)
+        if (hipEventCreate(&ev[nev]) != hipSuccess) break;
+    if (nev < 2 * reps) {
+        for (int k = 0; k < nev; ++k) hipEventDestroy(ev[k]);
         return SPT_EHIP;
     }
     float bms = 1e30f;
     spt_tune bt{0, 0, 0, 0, 0};
     int tried = 0;
     rc = SPT_OK;
+    auto consider = [&](const spt_tune &r) {
+        float ms = 0.f;
+        rc = time_config(X, mode, R, factors, fdtype, V, r, reps, ev, s, &ms);
+        if (rc) return;
+        ++tried;
+        if (ms < bms) {
+            bms = ms;
+            bt = r;
+        }
+    };
+    // the library's own default first: its layout and the chunk its launch really uses (which
+    // may be matched to the device's resident wavefronts), whenever the flags allow it
+    {
+        spt_tune r;
+        if (spt_mttkrp_default_tune(X, mode, R, fdtype, SPT_ALGO_AUTO, &r) == SPT_OK) {
+            const bool is_perm = r.algo != SPT_ALGO_ATOMIC && r.algo != SPT_ALGO_PRIVATIZED;
+            const bool allowed =
+                !(is_perm && (flags & SPT_TUNE_NO_PERMUTED)) &&
+                !(!is_perm && (flags & SPT_TUNE_NO_ATOMIC)) &&
+                !(batch_only && !spt_batch_supported_tune(X->d, fdtype, r.algo, r.lanes_per_nnz,
+                                                          r.cols_per_lane));
+            if (allowed) consider(r);
+        }
+    }
     for (int algo = SPT_ALGO_ATOMIC; algo <= SPT_ALGO_PRIVATIZED && rc == SPT_OK; ++algo) {
         if (algo == SPT_ALGO_PRIVATIZED && (batch_only || (flags & SPT_TUNE_NO_ATOMIC))) continue;
         if (algo == SPT_ALGO_PERMUTED && (!X->permuted[mode] || (flags & SPT_TUNE_NO_PERMUTED)))
@@ -360,35 +415,17 @@ extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
             if (G * CPL < R || R % CPL != 0) continue;
             if (G * CPL >= 2 * R && G * CPL > 16) continue;
             if (batch_only && !spt_batch_supported_tune(X->d, fdtype, algo, G, CPL)) continue;
-            const int lalgo = (algo == SPT_ALGO_ATOMIC) ? SPT_ALGO_ATOMIC : SPT_ALGO_PERMUTED;
-            (void)lalgo;
             for (int chunk : chunks) {
                 if (algo == SPT_ALGO_PRIVATIZED && chunk != chunks[0]) break;  // chunk is derived
                 spt_tune t{algo, G, CPL, chunk, 0}, r;
                 if (resolve_tune(X, mode, R, fdtype, &t, &r) != SPT_OK) continue;
-                rc = launch_mttkrp(X, mode, R, factors, fdtype, nullptr, nullptr, V, r, s);
+                consider(r);
                 if (rc) break;
-                hipEventRecord(e0, s);
-                for (int k = 0; k < reps && rc == SPT_OK; ++k)
-                    rc = launch_mttkrp(X, mode, R, factors, fdtype, nullptr, nullptr, V, r, s);
-                hipEventRecord(e1, s);
-                if (rc || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = rc ? rc : SPT_EHIP;
-                    break;
-                }
-                float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
-                ms /= reps;
-                ++tried;
-                if (ms < bms) {
-                    bms = ms;
-                    bt = r;
-                }
             }
+            if (rc) break;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    for (int k = 0; k < nev; ++k) hipEventDestroy(ev[k]);
     if (rc) return rc;
     if (tried == 0) return SPT_EUNSUPPORTED;
     *best = bt;
