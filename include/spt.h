@@ -261,7 +261,11 @@ int spt_batch_destroy(spt_batch *B);
  * factors: host array of d device pointers (I_m x R, fdtype), A^(n) overwritten.
  * lambda: device R doubles (overwritten).  grams: device d x R x R doubles, G_m for every mode
  * on entry (spt_cp_gram), G_n overwritten.  ws: device workspace of spt_cp_workspace_bytes().
- * R must be <= 64. */
+ * R: 1 .. 64 any value (Cholesky in one wavefront, row-parallel substitution); 65 .. 256 as for
+ * spt_mttkrp (even up to 128, multiples of 4 above), where the Cholesky factor of Gamma and its
+ * inverse are formed by one workgroup and the row solves run as one FP64 product V Gamma^-1
+ * (the two agree to about cond(Gamma) times the FP64 rounding unit); SPT_EUNSUPPORTED
+ * otherwise.  spt_cp_gram needs ws of R x R x 8 x (1024 up to R = 64, else 64) bytes. */
 size_t spt_cp_workspace_bytes(const spt_tensor *X, int R);
 
 int spt_cp_gram(int64_t I, int R, const void *A, int fdtype, double *G, void *ws,
@@ -335,7 +339,7 @@ int spt_model_values(const spt_tensor *X, int R, const void *const *factors, int
  *   backward: y_i = g w_i (exp(m_i) - x_i) into y (device P values, scratch), g = *gscale
  *             (device double, the upstream gradient; NULL = 1), then grads[n] = MTTKRP(Y, A, n)
  *             for every mode (host array of d device I_n x R buffers, double for F64 else float)
- * w: device P weights or NULL (all ones).  R <= 64 for the forward pass. */
+ * w: device P weights or NULL (all ones).  R as for spt_cp_als_mode (at most 256). */
 int spt_gcp_poisson_forward(const spt_tensor *X, int R, const void *const *factors, int fdtype,
                             const void *w, void *m, double *loss, void *ws, size_t ws_bytes,
                             void *stream);

@@ -253,7 +253,7 @@ class CPState:
         self.grams = torch.empty((X.d, self.R, self.R), dtype=torch.float64, device=dev)
         nbytes = lib.spt_cp_workspace_bytes(X.handle, self.R)
         if nbytes == 0:
-            raise SptError(_lib.SPT_EUNSUPPORTED, "spt_cp_workspace_bytes (R must be <= 64)")
+            raise SptError(_lib.SPT_EUNSUPPORTED, "spt_cp_workspace_bytes (R must be <= 256)")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self._last_mode = None  # mode whose MTTKRP the workspace holds (for the fast fit)
         for m, f in enumerate(self.factors):

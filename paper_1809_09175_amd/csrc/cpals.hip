@@ -10,14 +10,19 @@
 
 namespace spt {
 
-constexpr int kCpMaxR = 64;
+constexpr int kCpSmallR = 64;       // register / LDS-resident kernels up to this rank
+constexpr int kCpMaxR = 256;        // largest rank of the CP-ALS and model calls
+constexpr int kBigGramParts = 64;   // partial Grams per call above kCpSmallR (64 x R x R doubles)
 constexpr int kGramRows = 64;       // rows staged per tile in the Gram kernel
 constexpr int kMaxPartBlocks = 1024;
 constexpr int kModelMaxBlocks = 2048;  // workgroups of the model pass (fit, GCP forward)
 
 struct CpWs {
-    size_t V, Y, L, gpart, cpart, misc, total;
+    size_t V, Y, L, Lx, Ginv, gpart, cpart, misc, total;
 };
+
+// partial Grams one Gram call writes (each R x R doubles)
+static int gram_parts(int R) { return R <= kCpSmallR ? kMaxPartBlocks : kBigGramParts; }
 
 static CpWs cp_layout(int64_t Imax, int R) {
     CpWs w;
@@ -28,8 +33,13 @@ static CpWs cp_layout(int64_t Imax, int R) {
     o += align256((size_t)Imax * R * 8);
     w.L = o;
     o += align256((size_t)R * R * 8);
+    w.Lx = o;    // above kCpSmallR: the Hadamard product, then the inverse of L
+    w.Ginv = o + (R > kCpSmallR ? align256((size_t)R * R * 8) : 0);  // and the inverse Gamma
+    o = w.Ginv + (R > kCpSmallR ? align256((size_t)R * R * 8) : 0);
     w.gpart = o;  // Gram / column partials (R x R per block), or fit partials (2 per block)
-    o += align256((size_t)std::max(kMaxPartBlocks * R * R, 2 * kModelMaxBlocks) * 8);
+    o += align256((size_t)std::max<size_t>((size_t)gram_parts(R) * R * R,
+                                           std::max<size_t>((size_t)kMaxPartBlocks * R,
+                                                            2 * kModelMaxBlocks)) * 8);
     w.cpart = o;  // Y^T Y
     o += align256((size_t)R * R * 8);
     w.misc = o;
@@ -80,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_gram_partial(const FT *__restrict__ 
                                                          const double *__restrict__ lambda,
                                                          FT *__restrict__ Aout, int64_t I, int R,
                                                          double *__restrict__ gpart) {
-    __shared__ double tile[kGramRows][kCpMaxR + 1];
+    __shared__ double tile[kGramRows][kCpSmallR + 1];
     const int tid = threadIdx.x;
     const int a0 = (tid >> 4) * B, b0 = (tid & 15) * B;
     double acc[B][B];
@@ -161,13 +171,13 @@ __global__ __launch_bounds__(kBlock) void k_hadamard_chol(const double *__restri
                                                           int n, int R, double *__restrict__ L,
                                                           SptStatusBlock *st) {
 #pragma clang fp contract(off)
-    __shared__ double S[kCpMaxR][kCpMaxR];
-    __shared__ double Lc[kCpMaxR][kCpMaxR];
+    __shared__ double S[kCpSmallR][kCpSmallR];
+    __shared__ double Lc[kCpSmallR][kCpSmallR];
     __shared__ double lcc_s;
     __shared__ int bad;
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
-    for (int e = tid; e < kCpMaxR * kCpMaxR; e += kBlock) Lc[e / kCpMaxR][e % kCpMaxR] = 0.0;
+    for (int e = tid; e < kCpSmallR * kCpSmallR; e += kBlock) Lc[e / kCpSmallR][e % kCpSmallR] = 0.0;
     for (int ab = tid; ab < R * R; ab += kBlock) {
         double g = 1.0;
         for (int m = 0; m < d; ++m)
@@ -400,6 +410,215 @@ __global__ void k_norms(const double *__restrict__ sq, int R, double *__restrict
 }
 
 // ------------------------------------------------------------------------------------------
+// Ranks above kCpSmallR (up to 256): Gamma, its Cholesky factor and its inverse in global memory
+// (L2-resident, R x R doubles each) with one workgroup, then the row solves as one FP64 GEMM
+// V Gamma^-1, then normalisation and the Gram of the stored factor in 64 x 64 output blocks.
+// ------------------------------------------------------------------------------------------
+
+// One workgroup, thread r owning row r of L (R <= 256 = kBlock).  Gamma = Hadamard product of
+// the other Grams into S; the Cholesky factor L column by column in the textbook order (row c of
+// L is broadcast through LDS before column step c; pivots <= R eps max diag raise
+// SPT_ESINGULAR); then X = L^-1 by forward substitution (thread j owns column j, written over
+// S) and Gamma^-1 = X^T X into Ginv.
+__global__ __launch_bounds__(kBlock) void k_chol_inverse_big(const double *__restrict__ grams,
+                                                             int d, int n, int R,
+                                                             double *__restrict__ S,
+                                                             double *__restrict__ L,
+                                                             double *__restrict__ Ginv,
+                                                             SptStatusBlock *st) {
+#pragma clang fp contract(off)
+    __shared__ double rowc[kCpMaxR];
+    __shared__ double lcc_s, maxdiag_s;
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    for (int ab = tid; ab < R * R; ab += kBlock) {
+        double g = 1.0;
+        for (int m = 0; m < d; ++m)
+            if (m != n) g *= grams[(int64_t)m * R * R + ab];
+        S[ab] = g;
+        L[ab] = 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double md = 0.0;
+        for (int k = 0; k < R; ++k) md = S[k * R + k] > md ? S[k * R + k] : md;
+        maxdiag_s = md;
+        bad = 0;
+    }
+    __syncthreads();
+    const double tol = (double)R * 2.220446049250313e-16 * maxdiag_s;
+    const int r = tid;
+    for (int c = 0; c < R; ++c) {
+        for (int k = tid; k < c; k += kBlock) rowc[k] = L[c * R + k];
+        __syncthreads();
+        if (r == c) {
+            double piv = S[c * R + c];
+            for (int k = 0; k < c; ++k) piv -= rowc[k] * rowc[k];
+            if (!(piv > tol)) {
+                bad = 1;
+                piv = 1.0;  // keep the factor finite; the status word reports the failure
+            }
+            lcc_s = sqrt(piv);
+            L[c * R + c] = lcc_s;
+        }
+        __syncthreads();
+        if (r > c && r < R) {
+            double v = S[r * R + c];
+            for (int k = 0; k < c; ++k) v -= L[r * R + k] * rowc[k];
+            L[r * R + c] = v / lcc_s;
+        }
+        __syncthreads();
+    }
+    // X = L^-1 (lower triangular), column j by thread j, over S
+    if (r < R) {
+        const int j = r;
+        for (int i = 0; i < j; ++i) S[i * R + j] = 0.0;
+        for (int i = j; i < R; ++i) {
+            double v = (i == j) ? 1.0 : 0.0;
+            for (int k = j; k < i; ++k) v -= L[i * R + k] * S[k * R + j];
+            S[i * R + j] = v / L[i * R + i];
+        }
+    }
+    __syncthreads();
+    // Gamma^-1 = X^T X: entry (i, j) sums X[k][i] X[k][j] over k >= max(i, j)
+    if (r < R) {
+        const int j = r;
+        for (int i = 0; i < R; ++i) {
+            double v = 0.0;
+            for (int k = (i > j ? i : j); k < R; ++k) v += S[k * R + i] * S[k * R + j];
+            Ginv[i * R + j] = v;
+        }
+    }
+    if (tid == 0 && bad) raise_status(st, SPT_ESINGULAR);
+}
+
+// Y = V Gamma^-1 (I x R times R x R, FP64 products and sums): 64 x 64 output tiles, the
+// reduction dimension in steps of 16 staged through LDS, 4 x 4 outputs per thread.
+constexpr int kGemmTile = 64, kGemmK = 16;
+
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_solve_gemm(const VT *__restrict__ V, int64_t I,
+                                                       int R, const double *__restrict__ Ginv,
+                                                       double *__restrict__ Y) {
+    __shared__ double As[kGemmTile][kGemmK + 1];
+    __shared__ double Bs[kGemmK][kGemmTile + 1];
+    const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+    const int64_t r0 = (int64_t)blockIdx.x * kGemmTile;
+    const int c0 = blockIdx.y * kGemmTile;
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int k0 = 0; k0 < R; k0 += kGemmK) {
+        for (int e = tid; e < kGemmTile * kGemmK; e += kBlock) {
+            const int rr = e / kGemmK, kk = e - rr * kGemmK;
+            const int64_t row = r0 + rr;
+            const int k = k0 + kk;
+            As[rr][kk] = (row < I && k < R) ? (double)V[row * R + k] : 0.0;
+        }
+        for (int e = tid; e < kGemmK * kGemmTile; e += kBlock) {
+            const int kk = e / kGemmTile, cc = e - kk * kGemmTile;
+            const int k = k0 + kk, c = c0 + cc;
+            Bs[kk][cc] = (k < R && c < R) ? Ginv[k * R + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGemmK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[x] = As[tr * 4 + x][kk];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) b[y] = Bs[kk][tc * 4 + y];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const int64_t row = r0 + tr * 4 + x;
+        if (row >= I) continue;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int c = c0 + tc * 4 + y;
+            if (c < R) Y[row * R + c] = acc[x][y];
+        }
+    }
+}
+
+// A = Y / lambda column by column (columns with lambda = 0 unscaled), stored in FT
+template <class FT>
+__global__ __launch_bounds__(kBlock) void k_normalize_store(const double *__restrict__ Y,
+                                                            const double *__restrict__ lambda,
+                                                            int64_t len, int R,
+                                                            FT *__restrict__ A) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < len; i += stride) {
+        double y = Y[i];
+        const double l = lambda[i % R];
+        if (l > 0.0) y = y / l;
+        store_from_f64<FT>(A + i, y);
+    }
+}
+
+// Partial Gram A^T A for one 64 x 64 output block (blockIdx.y = block row * nbk + block column)
+// over a range of rows (blockIdx.x of gridDim.x): rows staged 32 at a time in LDS, 4 x 4 outputs
+// per thread, each entry summing its rows in increasing order.
+constexpr int kBigGramRows = 32;
+
+template <class FT>
+__global__ __launch_bounds__(kBlock) void k_gram_big_partial(const FT *__restrict__ A, int64_t I,
+                                                             int R, double *__restrict__ gpart) {
+    __shared__ double Ta[kBigGramRows][kGemmTile + 1];
+    __shared__ double Tb[kBigGramRows][kGemmTile + 1];
+    const int tid = threadIdx.x, ta = tid / 16, tb = tid % 16;
+    const int nbk = (R + kGemmTile - 1) / kGemmTile;
+    const int bi = blockIdx.y / nbk, bj = blockIdx.y - bi * nbk;
+    const int ca = bi * kGemmTile, cb = bj * kGemmTile;
+    const int64_t per = ceil_div(ceil_div(I, (int64_t)gridDim.x), (int64_t)kBigGramRows) * kBigGramRows;
+    const int64_t rbeg = (int64_t)blockIdx.x * per;
+    const int64_t rend = (rbeg + per < I) ? rbeg + per : I;
+    double acc[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    for (int64_t r0 = rbeg; r0 < rend; r0 += kBigGramRows) {
+        for (int e = tid; e < kBigGramRows * kGemmTile; e += kBlock) {
+            const int rr = e / kGemmTile, cc = e - rr * kGemmTile;
+            const int64_t row = r0 + rr;
+            const bool ok = row < rend;
+            Ta[rr][cc] = (ok && ca + cc < R) ? load_f64<FT>(A + row * R + ca + cc) : 0.0;
+            Tb[rr][cc] = (ok && cb + cc < R) ? load_f64<FT>(A + row * R + cb + cc) : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < kBigGramRows; ++rr) {
+            double a[4], b[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[x] = Ta[rr][ta * 4 + x];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) b[y] = Tb[rr][tb * 4 + y];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+    }
+    double *out = gpart + (int64_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int a = ca + ta * 4 + x, b = cb + tb * 4 + y;
+            if (a < R && b < R) out[a * R + b] = acc[x][y];
+        }
+}
+
+// ------------------------------------------------------------------------------------------
 // Fit / model values / GCP forward: one pass over the stored entries in storage order.
 // Lane groups of G lanes evaluate one entry: each lane forms lambda_j prod_m A^(m)(l_m, j) for
 // its column, the group sums over columns.
@@ -624,10 +843,23 @@ static void model_layout(int R, int *G, int *CPL) {
             *CPL = c;
             return;
         }
-    int g = 16;
-    while (g < R) g <<= 1;
-    *G = g;
-    *CPL = 1;
+    if (R <= 64) {
+        int g = 16;
+        while (g < R) g <<= 1;
+        *G = g;
+        *CPL = 1;
+        return;
+    }
+    // above 64 columns: 32 or 64 lanes with several columns each (CPL must divide R)
+    const int wide[][2] = {{32, 4}, {64, 2}, {32, 8}, {64, 4}};
+    for (const auto &w : wide)
+        if (R % w[1] == 0 && w[0] * w[1] >= R) {
+            *G = w[0];
+            *CPL = w[1];
+            return;
+        }
+    *G = 0;  // no compiled layout: the caller reports SPT_EUNSUPPORTED
+    *CPL = 0;
 }
 
 constexpr int kModelChunk = 2048;  // entries per wavefront chunk of the model pass
@@ -664,6 +896,10 @@ static int launch_model_d(const spt_tensor *X, int R, const FactorSet<FT> &A,
         SPT_MODEL_CFG(16, 1)
         SPT_MODEL_CFG(32, 1)
         SPT_MODEL_CFG(64, 1)
+        SPT_MODEL_CFG(32, 4)
+        SPT_MODEL_CFG(32, 8)
+        SPT_MODEL_CFG(64, 2)
+        SPT_MODEL_CFG(64, 4)
         default: return SPT_EUNSUPPORTED;
     }
 #undef SPT_MODEL_CFG
@@ -717,9 +953,44 @@ static int launch_gram(const FT *Ain, const double *Y, const double *lambda, FT 
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
 }
 
+template <class FT>
+static int launch_gram_big(const FT *A, const double *Y, const double *lambda, FT *Aout,
+                           int64_t I, int R, double *gpart, double *G, hipStream_t s) {
+    if (Y != nullptr) {  // normalise and store first, then the Gram of the stored values
+        const int64_t len = I * (int64_t)R;
+        int64_t nb = ceil_div(len, kBlock);
+        if (nb > 65536) nb = 65536;
+        hipLaunchKernelGGL((k_normalize_store<FT>), dim3((unsigned)nb), dim3(kBlock), 0, s, Y,
+                           lambda, len, R, Aout);
+        A = Aout;
+    }
+    const int nbk = (R + kGemmTile - 1) / kGemmTile;
+    const int parts = (int)std::min<int64_t>(kBigGramParts,
+                                             std::max<int64_t>(1, ceil_div(I, kBigGramRows)));
+    hipLaunchKernelGGL((k_gram_big_partial<FT>), dim3((unsigned)parts, (unsigned)(nbk * nbk)),
+                       dim3(kBlock), 0, s, A, I, R, gpart);
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)ceil_div(R * R, kBlock / kWave)), dim3(kBlock), 0,
+                       s, gpart, parts, R * R, G);
+    return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
+}
+
 static int gram_any(int fdtype, const void *Ain, const double *Y, const double *lambda,
                     void *Aout, int64_t I, int R, double *gpart, double *G, bool norm,
                     hipStream_t s) {
+    if (R > kCpSmallR) {
+        switch (fdtype) {
+            case SPT_F64:
+                return launch_gram_big<double>((const double *)Ain, norm ? Y : nullptr, lambda,
+                                               (double *)Aout, I, R, gpart, G, s);
+            case SPT_F32:
+                return launch_gram_big<float>((const float *)Ain, norm ? Y : nullptr, lambda,
+                                              (float *)Aout, I, R, gpart, G, s);
+            case SPT_BF16:
+                return launch_gram_big<uint16_t>((const uint16_t *)Ain, norm ? Y : nullptr, lambda,
+                                                 (uint16_t *)Aout, I, R, gpart, G, s);
+            default: return SPT_EINVAL;
+        }
+    }
     switch (fdtype) {
         case SPT_F64:
             return norm ? launch_gram<double, true>(nullptr, Y, lambda, (double *)Aout, I, R, gpart, G, s)
@@ -833,7 +1104,7 @@ int spt_cp_gram(int64_t I, int R, const void *A, int fdtype, double *G, void *ws
                 size_t ws_bytes, void *stream) {
     if (I < 1 || R < 1 || R > kCpMaxR || A == nullptr || G == nullptr || ws == nullptr)
         return SPT_EINVAL;
-    if (ws_bytes < (size_t)kMaxPartBlocks * R * R * 8 || ((uintptr_t)ws & 255u))
+    if (ws_bytes < (size_t)gram_parts(R) * R * R * 8 || ((uintptr_t)ws & 255u))
         return SPT_EWORKSPACE;
     return gram_any(fdtype, A, nullptr, nullptr, nullptr, I, R, static_cast<double *>(ws), G,
                     false, static_cast<hipStream_t>(stream));
@@ -869,19 +1140,35 @@ int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fd
     // V = MTTKRP with the other (normalised) factors and unit weights
     rc = launch_mttkrp(X, mode, R, (const void *const *)factors, fdtype, nullptr, nullptr, V, t, s);
     if (rc) return rc;
-    if (R <= 16)
-        hipLaunchKernelGGL(k_hadamard_chol<16>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
-                           Lf, X->status);
-    else if (R <= 32)
-        hipLaunchKernelGGL(k_hadamard_chol<32>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
-                           Lf, X->status);
-    else
-        hipLaunchKernelGGL(k_hadamard_chol<64>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
-                           Lf, X->status);
-    SPT_LAUNCH_CHECK();
-    rc = (fdtype == SPT_F64) ? launch_solve<double>((const double *)V, I, R, Lf, Y, s)
-                             : launch_solve<float>((const float *)V, I, R, Lf, Y, s);
-    if (rc) return rc;
+    if (R > kCpSmallR) {
+        // Gamma, L and Gamma^-1 in one workgroup; the row solves as one GEMM V Gamma^-1
+        double *Sx = reinterpret_cast<double *>(w + L.Lx);
+        double *Gi = reinterpret_cast<double *>(w + L.Ginv);
+        hipLaunchKernelGGL(k_chol_inverse_big, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
+                           Sx, Lf, Gi, X->status);
+        const dim3 g((unsigned)ceil_div(I, (int64_t)kGemmTile), (unsigned)ceil_div(R, kGemmTile));
+        if (fdtype == SPT_F64)
+            hipLaunchKernelGGL((k_solve_gemm<double>), g, dim3(kBlock), 0, s,
+                               static_cast<const double *>(V), I, R, Gi, Y);
+        else
+            hipLaunchKernelGGL((k_solve_gemm<float>), g, dim3(kBlock), 0, s,
+                               static_cast<const float *>(V), I, R, Gi, Y);
+        SPT_LAUNCH_CHECK();
+    } else {
+        if (R <= 16)
+            hipLaunchKernelGGL(k_hadamard_chol<16>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode,
+                               R, Lf, X->status);
+        else if (R <= 32)
+            hipLaunchKernelGGL(k_hadamard_chol<32>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode,
+                               R, Lf, X->status);
+        else
+            hipLaunchKernelGGL(k_hadamard_chol<64>, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode,
+                               R, Lf, X->status);
+        SPT_LAUNCH_CHECK();
+        rc = (fdtype == SPT_F64) ? launch_solve<double>((const double *)V, I, R, Lf, Y, s)
+                                 : launch_solve<float>((const float *)V, I, R, Lf, Y, s);
+        if (rc) return rc;
+    }
     // column 2-norms of the FP64 solution
     {
         int64_t nb = ceil_div(I, (int64_t)kGramRows);

@@ -57,7 +57,7 @@ static int gcp_dtype_ok(const spt_tensor *X, int fdtype) {
 int spt_gcp_forward(const spt_tensor *X, int R, const void *const *factors, int fdtype,
                     int loss_kind, const void *w, void *m, double *loss, void *ws,
                     size_t ws_bytes, void *stream) {
-    if (X == nullptr || R < 1 || R > 64 || m == nullptr || loss == nullptr) return SPT_EINVAL;
+    if (X == nullptr || R < 1 || R > 256 || m == nullptr || loss == nullptr) return SPT_EINVAL;
     if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAMMA) return SPT_EINVAL;
     if (int e = gcp_dtype_ok(X, fdtype)) return e;
     int rc = check_factors(X, -1, factors);

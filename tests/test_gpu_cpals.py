@@ -123,10 +123,13 @@ def test_cp_mode_update_low_precision(gpu, kind):
             assert np.array_equal(st.factors[n].cpu().numpy(), a.astype(np.float32)), n
 
 
-@pytest.mark.parametrize("R", [5, 20, 40, 64])
+@pytest.mark.parametrize("R", [5, 20, 40, 64, 96, 128, 200, 256])
 def test_cp_mode_update_fp64_ranks(gpu, R):
-    """FP64 mode updates at ranks off the 16/32/64 grid (padded Cholesky, solve and Gram tiles)
-    and at the largest rank, against the oracle's mode update from the same state."""
+    """FP64 mode updates at ranks off the 16/32/64 grid (padded Cholesky, solve and Gram tiles),
+    at 64 (the largest of the one-wavefront Cholesky) and above it up to 256 (Cholesky and
+    inverse in one workgroup, the row solves as one product with the inverse, 64 x 64 Gram
+    blocks, partial last blocks at 96 and 200), against the oracle's mode update from the same
+    state."""
     import paper_1809_09175_amd as spt
     X = _skewed4_small()
     X.vals = X.vals.astype(np.float64)
@@ -276,16 +279,84 @@ def test_fit_rank_one_many_entries(gpu):
     assert abs(st.fit(source="mttkrp") - f_ref) < 1e-11
 
 
-def test_model_values(gpu):
+@pytest.mark.parametrize("R", [24, 96, 128, 256])
+def test_model_values(gpu, R):
+    """Model values of every stored entry, including the wide lane layouts above 64 columns."""
     import paper_1809_09175_amd as spt
     X = _skewed4_small()
-    A = datagen.factors(X.dims, 24, seed=1, dtype=np.float64)
+    A = datagen.factors(X.dims, R, seed=1, dtype=np.float64)
     X.vals = X.vals.astype(np.float64)
     T = _dev_tensor(X, np.float64)
-    lam = np.linspace(1.0, 2.0, 24)
+    lam = np.linspace(1.0, 2.0, R)
     m = spt.model_values(T, [torch.from_numpy(a).cuda() for a in A],
                          torch.from_numpy(lam).cuda())
     assert _relerr(m.cpu().numpy(), oracle.model_values(X.subs, X.dims, A, lam)) < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["f64", "f32", "bf16"])
+def test_large_rank_mode_update_fit_and_loss(gpu, kind):
+    """R = 128: a CP-ALS mode update against the oracle from the same state (FP32 and BF16
+    factors at the tolerance of their MTTKRP mapped through Gamma^-1, as for R <= 64), the
+    stored factor bit-exact against the FP64 solution rounded once, the entry-pass and
+    allocation-free fits and the generalized-CP (Poisson) loss against the oracle."""
+    import ctypes
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import _lib
+    X = _skewed4_small()
+    R = 128
+    vdt = np.float64 if kind == "f64" else np.float32
+    X.vals = X.vals.astype(vdt)
+    T = _dev_tensor(X, vdt)
+    T.permute()
+    A = datagen.factors(X.dims, R, seed=12, dtype=vdt)
+    dev = [torch.from_numpy(a.copy()).cuda() for a in A]
+    if kind == "bf16":
+        dev = [spt.to_bf16(a) for a in dev]
+    st = spt.CPState(T, dev)
+    Ain = [_np(f) for f in st.factors]
+    Gin = st.grams.cpu().numpy()
+    assert _relerr(Gin, np.stack([a.T @ a for a in Ain])) < 1e-12
+    st.mode_update(1)
+    Ao, lo, Go = oracle.cp_als_mode(X.subs, X.vals, X.dims, Ain, np.ones(R), Gin, 1)
+    Gam = Gin[0] * Gin[2] * Gin[3]
+    cond = np.linalg.cond(Gam)
+    tol = 1e-13 * max(1.0, cond) if kind == "f64" else max(1e-5, 1e-6 * cond)
+    if kind == "bf16":
+        tol += 2.0 ** -8
+    assert _relerr(_np(st.factors[1]), Ao[1]) < tol, cond
+    assert _relerr(st.lam.cpu().numpy(), lo) < tol
+    stored = _np(st.factors[1])
+    assert _relerr(st.grams[1].cpu().numpy(), stored.T @ stored) < 1e-12
+    Y = st.solution().cpu().numpy()
+    lam = st.lam.cpu().numpy()
+    a = np.where(lam > 0, Y / np.where(lam > 0, lam, 1.0), Y)
+    if kind == "bf16":
+        bits = st.factors[1].view(torch.int16).cpu().numpy().view(np.uint16)
+        assert np.array_equal(bits, oracle.bf16_rne_f64(a))
+    else:
+        assert np.array_equal(st.factors[1].cpu().numpy(), a.astype(vdt))
+    # fits of the updated state (from the stored entries, with and without a workspace)
+    Acur = [_np(f) for f in st.factors]
+    f_ref = oracle.fit(X.subs, X.vals, X.dims, Acur, lam)
+    f = st.fit()
+    assert abs(f - f_ref) < 1e-12 * max(1.0, abs(f_ref))
+    fna = ctypes.c_double()
+    parts = (ctypes.c_double * 3)()
+    assert _lib.load().spt_cp_fit_noalloc(T.handle, R, st._fptrs(), st.fdtype,
+                                          ctypes.c_void_p(st.lam.data_ptr()),
+                                          ctypes.c_void_p(st.grams.data_ptr()),
+                                          ctypes.byref(fna), parts, None) == 0
+    assert fna.value == f
+    if kind == "bf16":
+        return
+    # generalized-CP loss at R = 128 (unfused forward), small factors so exp(m) stays moderate
+    facs = [torch.from_numpy((a * 0.05).astype(vdt)).cuda().requires_grad_(True) for a in A]
+    loss = spt.GCPPoissonLoss.apply(T, torch.ones(X.nnz, dtype=facs[0].dtype, device="cuda"),
+                                    *facs)
+    loss_ref = oracle.gcp_poisson(X.subs, X.vals, X.dims,
+                                  [(a * 0.05).astype(vdt).astype(np.float64) for a in A],
+                                  grads=False)
+    assert abs(loss.item() - loss_ref) < (1e-12 if kind == "f64" else 1e-5) * abs(loss_ref)
 
 
 def test_singular_gram_reported(gpu):
