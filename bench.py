@@ -272,6 +272,52 @@ def bench_shard_share(spt, torch, T, X, dev, R, shards=8):
     return {"entries_per_shard": X.nnz // shards, "rank": R, "mttkrp_ms_per_mode": out}
 
 
+def bench_ingest(spt, torch, X, dev, chunk=1 << 23, reps=2):
+    """Host arrays in pinned memory to a permuted tensor (every mode): one whole copy, then
+    packing and the sort, against chunked ingest, where chunk k+1 is copied while chunk k is
+    packed and its first radix digit counted.  Wall-clock time of the second of `reps` runs of
+    each (the first warms the allocator), synchronised at both ends."""
+    hs = torch.from_numpy(X.subs).pin_memory()
+    hv = torch.from_numpy(X.vals).pin_memory()
+
+    def serial():
+        subs = hs.to(dev, non_blocking=True)
+        vals = hv.to(dev, non_blocking=True)
+        T = spt.SparseTensor(subs, vals, X.dims)
+        T.permute()
+        return T
+
+    def overlapped():
+        T = spt.SparseTensor.from_host(hs, hv, X.dims, chunk=chunk)
+        T.permute()
+        return T
+
+    res = {}
+    for name, fn in (("whole_copy_then_pack_ms", serial), ("chunked_overlap_ms", overlapped)):
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            T = fn()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            T.close()
+            del T
+        res[name] = round(ms, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d_s = hs.to(dev, non_blocking=True)
+    d_v = hv.to(dev, non_blocking=True)
+    torch.cuda.synchronize()
+    res["pinned_h2d_only_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    del d_s, d_v, hs, hv
+    torch.cuda.empty_cache()
+    res["chunk_entries"] = chunk
+    res["overlap_gain_ms"] = round(res["whole_copy_then_pack_ms"] - res["chunked_overlap_ms"], 2)
+    log(f"ingest to permuted: whole copy then pack {res['whole_copy_then_pack_ms']} ms, "
+        f"chunked overlap {res['chunked_overlap_ms']} ms (copy alone {res['pinned_h2d_only_ms']} ms)")
+    return res
+
+
 def bench_gcp(spt, datagen, torch, dev, R=32, steps=3):
     """Generalized CP (Poisson log link) forward + backward on the count tensor: 5e7 nonzeros
     plus 5e7 sampled zeros; the backward is one MTTKRP per mode of the derivative tensor."""
@@ -670,6 +716,7 @@ def main():
         extras["sorted_copy_ms_all_modes"] = round(copy_ms, 3)
         extras["ingest_h2d_ms"] = round(h2d_ms, 1)
         extras["ingest_pack_validate_ms"] = round(pack_ms, 1)
+        extras["ingest_to_permuted"] = bench_ingest(spt, torch, X, dev)
         # memory side of the trade: one record array per mode beside the records themselves
         lib = spt._lib.load()
         extras["sorted_copy_bytes_all_modes"] = int(lib.spt_tensor_sorted_copy_bytes(T.handle, -1, 1))

@@ -125,6 +125,22 @@ int spt_tensor_create(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
                       const int32_t *subs, const void *vals, int vals_dtype, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* The same in pieces, so that moving the entries to the device can overlap with packing them
+ * (Sec. 8 proposes building the permutation while the tensor is read): spt_tensor_create_begin
+ * takes the arguments of spt_tensor_create without subs and vals; then spt_tensor_append packs
+ * entries [first, first + count) from device arrays holding just those entries (subs: count x d
+ * int32, vals: count values), in order: first must equal the entries appended so far and be a
+ * multiple of 8192, count a multiple of 8192 unless the chunk ends the tensor (SPT_EINVAL /
+ * SPT_ESTATE otherwise).  Each append also counts the first radix digit (bits 0-7) of every
+ * mode's subscripts over its entries, which spt_tensor_permute then uses instead of a histogram
+ * pass of its own.  Until every entry is appended, spt_tensor_permute and the calls that read
+ * the entries return SPT_ESTATE.  spt_tensor_create is begin plus one append of all entries.
+ * Both enqueue only; the chunk's arrays are read by the enqueued work. */
+int spt_tensor_create_begin(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
+                            int vals_dtype, void *ws, size_t ws_bytes, void *stream);
+int spt_tensor_append(spt_tensor *X, int64_t first, int64_t count, const int32_t *subs,
+                      const void *vals, void *stream);
+
 /* Synchronises `stream`; returns SPT_ERANGE (and the first offending entry index in *bad_entry
  * when not NULL) if a subscript was out of range, else the pending device status. */
 int spt_tensor_validate(const spt_tensor *X, int64_t *bad_entry, void *stream);

@@ -93,6 +93,66 @@ class SparseTensor:
         self._h = h
         self._keep = (subs, vals)   # alive until the packing work has run
 
+    @classmethod
+    def from_host(cls, subs, vals, dims, chunk: int = 1 << 23, device="cuda", stream=None):
+        """Builds the tensor from host arrays (numpy or CPU torch tensors; (P, d) int32
+        subscripts, (P,) float32/float64 values) in chunks of `chunk` entries (a multiple of
+        8192): each chunk is copied to the device on a copy stream of its own while the previous
+        chunk is packed (spt_tensor_append, which also counts the first radix digit of every
+        mode).  The copies run asynchronously from pinned host memory (torch's pin_memory());
+        from pageable memory each copy is staged by the runtime and overlaps less."""
+        if chunk <= 0 or chunk % 8192:
+            raise ValueError("chunk must be a positive multiple of 8192")
+        subs = torch.as_tensor(subs)
+        vals = torch.as_tensor(vals)
+        if subs.dtype != torch.int32 or subs.dim() != 2 or subs.device.type != "cpu":
+            raise ValueError("subs must be a (P, d) int32 host array")
+        if vals.dtype not in (torch.float32, torch.float64) or vals.shape != (subs.shape[0],) \
+                or vals.device.type != "cpu":
+            raise ValueError("vals must be (P,) float32 or float64 host values")
+        self = cls.__new__(cls)
+        lib = _lib.load()
+        self.d = int(subs.shape[1])
+        self.dims = tuple(int(x) for x in dims)
+        if len(self.dims) != self.d:
+            raise ValueError("dims must have d entries")
+        self.nnz = int(subs.shape[0])
+        self.device = torch.device(device)
+        self.vdtype = SPT_F64 if vals.dtype == torch.float64 else SPT_F32
+        self.vals_dtype = vals.dtype
+        dims_arr = (ctypes.c_int64 * self.d)(*self.dims)
+        nbytes = lib.spt_tensor_workspace_bytes(self.d, dims_arr, self.nnz, self.vdtype)
+        if nbytes == 0:
+            raise ValueError("unsupported tensor shape (order must be 2..5, dims < 2^31)")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        subs_d = torch.empty(subs.shape, dtype=torch.int32, device=self.device)
+        vals_d = torch.empty(vals.shape, dtype=vals.dtype, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            compute = stream if stream is not None else torch.cuda.current_stream()
+            _lib.check(lib.spt_tensor_create_begin(ctypes.byref(h), self.d, dims_arr, self.nnz,
+                                                   self.vdtype,
+                                                   ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                                   _stream(compute)), "spt_tensor_create_begin")
+            self._h = h
+            copy = torch.cuda.Stream(device=self.device)
+            copy.wait_stream(compute)   # the device buffers come from the compute stream
+            for a in range(0, self.nnz, chunk):
+                b = min(self.nnz, a + chunk)
+                with torch.cuda.stream(copy):
+                    subs_d[a:b].copy_(subs[a:b], non_blocking=True)
+                    vals_d[a:b].copy_(vals[a:b], non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(copy)
+                compute.wait_event(ev)
+                _lib.check(lib.spt_tensor_append(
+                    h, a, b - a, ctypes.c_void_p(subs_d[a:b].data_ptr()),
+                    ctypes.c_void_p(vals_d[a:b].data_ptr()), _stream(compute)), "spt_tensor_append")
+            subs_d.record_stream(compute)
+            vals_d.record_stream(compute)
+        self._keep = (subs_d, vals_d, subs, vals)   # alive until the packing work has run
+        return self
+
     @property
     def handle(self):
         return self._h

@@ -40,6 +40,8 @@ SIGNATURES = {
     "spt_version": (_c_i, []),
     "spt_tensor_workspace_bytes": (_c_sz, [_c_i, _c_p, _c_i64, _c_i]),
     "spt_tensor_create": (_c_i, [_c_p, _c_i, _c_p, _c_i64, _c_p, _c_p, _c_i, _c_p, _c_sz, _c_p]),
+    "spt_tensor_create_begin": (_c_i, [_c_p, _c_i, _c_p, _c_i64, _c_i, _c_p, _c_sz, _c_p]),
+    "spt_tensor_append": (_c_i, [_c_p, _c_i64, _c_i64, _c_p, _c_p, _c_p]),
     "spt_tensor_validate": (_c_i, [_c_p, _c_p, _c_p]),
     "spt_tensor_status": (_c_i, [_c_p, _c_p]),
     "spt_tensor_permute": (_c_i, [_c_p, _c_i, _c_p]),

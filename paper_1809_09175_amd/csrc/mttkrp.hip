@@ -231,6 +231,7 @@ static int check_dtypes(const spt_tensor *X, int fdtype) {
 
 int check_factors(const spt_tensor *X, int skip_mode, const void *const *factors) {
     if (factors == nullptr) return SPT_EINVAL;
+    if (X->appended != X->P) return SPT_ESTATE;  // entries still to be appended
     for (int m = 0; m < X->d; ++m)
         if (m != skip_mode && factors[m] == nullptr) return SPT_EINVAL;
     return SPT_OK;

@@ -35,6 +35,9 @@ struct spt_tensor {
     uint32_t *scan_part; // per-segment partial sums of the counts scan
     double *red;         // reduction scratch (fit, loss): kRedSlots doubles
     int permuted[SPT_MAX_ORDER];
+    uint32_t *hist0;     // first-pass digit counts of every mode (256 x ntiles each), filled
+                         // while packing
+    int64_t appended;    // entries packed so far (spt_tensor_append); all P once created
     double xx;           // ||X||^2 of the stored values, once xx_valid (the values never change)
     int xx_valid;
 };

@@ -13,45 +13,87 @@ namespace spt {
 // packing: P x d int32 subscripts + values -> records {l_0 .. l_{d-1}, pad, value}
 // ------------------------------------------------------------------------------------------
 
+// Packing of whole sort tiles (kSortTile entries per workgroup, the element order of the radix
+// kernels) that also counts the first radix digit (bits 0-7) of every mode's subscript, so the
+// first sort pass of each mode needs no histogram pass of its own: counts[m][digit][tile] for
+// the tiles tile0 .. tile0 + gridDim.x - 1.  Out-of-range subscripts are packed (and counted) as
+// 0 and reported, as by k_pack.
 template <class VT, int RW>
-__global__ __launch_bounds__(kBlock) void k_pack(const int32_t *__restrict__ subs,
-                                                  const VT *__restrict__ vals, int d, int64_t P,
-                                                  int4 *__restrict__ rec, SptStatusBlock *st,
-                                                  int64_t dim0, int64_t dim1, int64_t dim2,
-                                                  int64_t dim3, int64_t dim4) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= P) return;
+__global__ __launch_bounds__(kBlock) void k_pack_tiles(const int32_t *__restrict__ subs,
+                                                        const VT *__restrict__ vals, int d,
+                                                        int64_t P, int64_t first, int64_t tile0,
+                                                        int64_t ntiles, int4 *__restrict__ rec,
+                                                        uint32_t *__restrict__ counts,
+                                                        SptStatusBlock *st, int64_t dim0,
+                                                        int64_t dim1, int64_t dim2, int64_t dim3,
+                                                        int64_t dim4) {
+    __shared__ uint32_t h[SPT_MAX_ORDER][256];
+    const int tid = threadIdx.x, lane = tid & 63;
     const int64_t dims[SPT_MAX_ORDER] = {dim0, dim1, dim2, dim3, dim4};
-    int32_t w[RW];
 #pragma unroll
-    for (int k = 0; k < RW; ++k) w[k] = 0;
-    bool bad = false;
+    for (int m = 0; m < SPT_MAX_ORDER; ++m) h[m][tid] = 0;
+    __syncthreads();
+    const int64_t tile = tile0 + blockIdx.x;
+    int64_t bad_min = INT64_MAX;
+    for (int sub = 0; sub < kSortSubs; ++sub) {
+        const int64_t base = tile * kSortTile + (int64_t)sub * kSortSub;
 #pragma unroll
-    for (int m = 0; m < SPT_MAX_ORDER; ++m) {
-        if (m < d) {
-            int32_t l = subs[i * d + m];
-            if (l < 0 || (int64_t)l >= dims[m]) {
-                bad = true;
-                l = 0;  // keep every later access in bounds
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t e = base + it * kBlock + tid;
+            const bool valid = e < P;
+            int32_t w[RW];
+#pragma unroll
+            for (int k = 0; k < RW; ++k) w[k] = 0;
+            if (valid) {
+                const int64_t i = e - first;  // position in the caller's chunk
+#pragma unroll
+                for (int m = 0; m < SPT_MAX_ORDER; ++m) {
+                    if (m < d) {
+                        int32_t l = subs[i * d + m];
+                        if (l < 0 || (int64_t)l >= dims[m]) {
+                            bad_min = e < bad_min ? e : bad_min;
+                            l = 0;  // keep every later access in bounds
+                        }
+                        w[m] = l;
+                    }
+                }
+                const VT v = vals[i];
+                if constexpr (sizeof(VT) == 8) {
+                    const uint64_t b = __double_as_longlong(v);
+                    w[RW - 2] = (int32_t)(uint32_t)b;
+                    w[RW - 1] = (int32_t)(uint32_t)(b >> 32);
+                } else {
+                    w[RW - 1] = __float_as_int(v);
+                }
+                int4 *out = rec + e * (RW / 4);
+                out[0] = make_int4(w[0], w[1], w[2], w[3]);
+                if constexpr (RW == 8) out[1] = make_int4(w[4], w[5], w[6], w[7]);
             }
-            w[m] = l;
+#pragma unroll
+            for (int m = 0; m < SPT_MAX_ORDER; ++m) {
+                if (m >= d) continue;  // uniform
+                // lanes holding the same digit are matched with eight ballots; the lowest of them
+                // adds the group's count
+                const uint32_t dg = valid ? ((uint32_t)w[m] & 255u) : 256u;
+                uint64_t mk = __ballot(dg < 256u);
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const bool bit = (dg >> b) & 1u;
+                    const uint64_t bb = __ballot(bit);
+                    mk &= bit ? bb : ~bb;
+                }
+                if (dg < 256u && (__ffsll((unsigned long long)mk) - 1) == lane)
+                    atomicAdd(&h[m][dg], (uint32_t)__popcll(mk));
+            }
         }
     }
-    VT v = vals[i];
-    if constexpr (sizeof(VT) == 8) {
-        uint64_t b = __double_as_longlong(v);
-        w[RW - 2] = (int32_t)(uint32_t)b;
-        w[RW - 1] = (int32_t)(uint32_t)(b >> 32);
-    } else {
-        w[RW - 1] = __float_as_int(v);
-    }
-    int4 *out = rec + i * (RW / 4);
-    out[0] = make_int4(w[0], w[1], w[2], w[3]);
-    if constexpr (RW == 8) out[1] = make_int4(w[4], w[5], w[6], w[7]);
-    if (bad) {
+    if (bad_min != INT64_MAX) {
         raise_status(st, SPT_ERANGE);
-        atomicMin((unsigned long long *)&st->bad_entry, (unsigned long long)i);
+        atomicMin((unsigned long long *)&st->bad_entry, (unsigned long long)bad_min);
     }
+    __syncthreads();
+    for (int m = 0; m < d; ++m)
+        counts[(int64_t)m * 256 * ntiles + (int64_t)tid * ntiles + tile] = h[m][tid];
 }
 
 __global__ void k_status_init(SptStatusBlock *st) {
@@ -318,7 +360,11 @@ static int permute_mode(spt_tensor *X, int n, hipStream_t s) {
         int32_t *ov = to_final ? X->perm[n] : X->tmp_vals;
         const int shift = pass * 8;
         dim3 g((unsigned)ntiles), b(kBlock);
-        if (pass == 0)
+        if (pass == 0 && X->hist0 != nullptr)
+            // counted while packing; the scan below works in place, so on a copy
+            SPT_HIP(hipMemcpyAsync(X->hist, X->hist0 + (size_t)n * L, (size_t)L * 4,
+                                   hipMemcpyDeviceToDevice, s));
+        else if (pass == 0)
             hipLaunchKernelGGL(k_radix_hist<true>, g, b, 0, s, ik, recw, X->rec_words, n, P,
                                shift, X->hist, ntiles);
         else
@@ -347,7 +393,7 @@ static int permute_mode(spt_tensor *X, int n, hipStream_t s) {
 // workspace layout -----------------------------------------------------------------------------
 
 struct WsLayout {
-    size_t status, rec, perm, skey, tmp_keys, tmp_vals, hist, scan_part, red, total;
+    size_t status, rec, perm, skey, tmp_keys, tmp_vals, hist, hist0, scan_part, red, total;
 };
 
 static bool layout(int d, const int64_t *dims, int64_t P, int vdtype, WsLayout *L) {
@@ -373,6 +419,8 @@ static bool layout(int d, const int64_t *dims, int64_t P, int vdtype, WsLayout *
     o += align256((size_t)P * 4);
     L->hist = o;
     o += align256((size_t)Lh * 4);
+    L->hist0 = o;
+    o += (size_t)d * align256((size_t)Lh * 4);
     L->scan_part = o;
     o += align256((size_t)(ceil_div(Lh, kScanSeg) + 1) * 4);
     L->red = o;
@@ -409,15 +457,13 @@ size_t spt_tensor_workspace_bytes(int d, const int64_t *dims, int64_t nnz, int v
     return L.total;
 }
 
-int spt_tensor_create(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
-                      const int32_t *subs, const void *vals, int vals_dtype, void *ws,
-                      size_t ws_bytes, void *stream) {
+int spt_tensor_create_begin(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
+                            int vals_dtype, void *ws, size_t ws_bytes, void *stream) {
     if (out == nullptr) return SPT_EINVAL;
     *out = nullptr;
     WsLayout L;
     if (d > SPT_MAX_ORDER && d >= 2) return SPT_EUNSUPPORTED;
     if (!layout(d, dims, nnz, vals_dtype, &L)) return SPT_EINVAL;
-    if (nnz > 0 && (subs == nullptr || vals == nullptr)) return SPT_EINVAL;
     if (ws == nullptr || ((uintptr_t)ws & 255u) != 0 || ws_bytes < L.total)
         return SPT_EWORKSPACE;
     spt_tensor *X = new (std::nothrow) spt_tensor;
@@ -441,39 +487,75 @@ int spt_tensor_create(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
     X->tmp_keys = reinterpret_cast<int32_t *>(w + L.tmp_keys);
     X->tmp_vals = reinterpret_cast<int32_t *>(w + L.tmp_vals);
     X->hist = reinterpret_cast<uint32_t *>(w + L.hist);
+    X->hist0 = nullptr;  // set once every tile has been packed
     X->scan_part = reinterpret_cast<uint32_t *>(w + L.scan_part);
     X->red = reinterpret_cast<double *>(w + L.red);
+    X->appended = 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, s, X->status);
     if (hipGetLastError() != hipSuccess) {
         delete X;
         return SPT_EHIP;
     }
+    *out = X;
+    return SPT_OK;
+}
+
+int spt_tensor_append(spt_tensor *X, int64_t first, int64_t count, const int32_t *subs,
+                      const void *vals, void *stream) {
+    if (X == nullptr || first < 0 || count < 1 || first + count > X->P) return SPT_EINVAL;
+    if (subs == nullptr || vals == nullptr) return SPT_EINVAL;
+    if (first % kSortTile != 0 || (count % kSortTile != 0 && first + count != X->P))
+        return SPT_EINVAL;
+    if (first != X->appended) return SPT_ESTATE;  // chunks arrive in order, once each
+    const int64_t ntiles = ceil_div(X->P, kSortTile);
+    const int64_t tile0 = first / kSortTile;
+    const int64_t nt = ceil_div(count, kSortTile);
+    uint32_t *counts = reinterpret_cast<uint32_t *>(
+        reinterpret_cast<uint8_t *>(X->hist) + align256((size_t)256 * ntiles * 4));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    dim3 g((unsigned)nt), b(kBlock);
+    const int64_t *dd = X->dims;
+    const int d = X->d;
+    if (X->vdtype == SPT_F64) {
+        if (X->rec_words == 4)
+            hipLaunchKernelGGL((k_pack_tiles<double, 4>), g, b, 0, s, subs,
+                               static_cast<const double *>(vals), d, X->P, first, tile0, ntiles,
+                               X->rec, counts, X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+        else
+            hipLaunchKernelGGL((k_pack_tiles<double, 8>), g, b, 0, s, subs,
+                               static_cast<const double *>(vals), d, X->P, first, tile0, ntiles,
+                               X->rec, counts, X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+    } else {
+        if (X->rec_words == 4)
+            hipLaunchKernelGGL((k_pack_tiles<float, 4>), g, b, 0, s, subs,
+                               static_cast<const float *>(vals), d, X->P, first, tile0, ntiles,
+                               X->rec, counts, X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+        else
+            hipLaunchKernelGGL((k_pack_tiles<float, 8>), g, b, 0, s, subs,
+                               static_cast<const float *>(vals), d, X->P, first, tile0, ntiles,
+                               X->rec, counts, X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
+    }
+    SPT_LAUNCH_CHECK();
+    X->appended = first + count;
+    if (X->appended == X->P) X->hist0 = counts;
+    return SPT_OK;
+}
+
+int spt_tensor_create(spt_tensor **out, int d, const int64_t *dims, int64_t nnz,
+                      const int32_t *subs, const void *vals, int vals_dtype, void *ws,
+                      size_t ws_bytes, void *stream) {
+    if (out == nullptr) return SPT_EINVAL;
+    *out = nullptr;
+    if (nnz > 0 && (subs == nullptr || vals == nullptr)) return SPT_EINVAL;
+    spt_tensor *X = nullptr;
+    int rc = spt_tensor_create_begin(&X, d, dims, nnz, vals_dtype, ws, ws_bytes, stream);
+    if (rc) return rc;
     if (nnz > 0) {
-        dim3 g((unsigned)ceil_div(nnz, kBlock)), b(kBlock);
-        const int64_t *dd = X->dims;
-        if (vals_dtype == SPT_F64) {
-            if (X->rec_words == 4)
-                hipLaunchKernelGGL((k_pack<double, 4>), g, b, 0, s, subs,
-                                   static_cast<const double *>(vals), d, nnz, X->rec,
-                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
-            else
-                hipLaunchKernelGGL((k_pack<double, 8>), g, b, 0, s, subs,
-                                   static_cast<const double *>(vals), d, nnz, X->rec,
-                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
-        } else {
-            if (X->rec_words == 4)
-                hipLaunchKernelGGL((k_pack<float, 4>), g, b, 0, s, subs,
-                                   static_cast<const float *>(vals), d, nnz, X->rec,
-                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
-            else
-                hipLaunchKernelGGL((k_pack<float, 8>), g, b, 0, s, subs,
-                                   static_cast<const float *>(vals), d, nnz, X->rec,
-                                   X->status, dd[0], dd[1], dd[2], dd[3], dd[4]);
-        }
-        if (hipGetLastError() != hipSuccess) {
+        rc = spt_tensor_append(X, 0, nnz, subs, vals, stream);
+        if (rc) {
             delete X;
-            return SPT_EHIP;
+            return rc;
         }
     }
     *out = X;
@@ -511,6 +593,7 @@ int spt_tensor_validate(const spt_tensor *X, int64_t *bad_entry, void *stream) {
 
 int spt_tensor_permute(spt_tensor *X, int mode, void *stream) {
     if (X == nullptr || mode < -1 || mode >= X->d) return SPT_EINVAL;
+    if (X->appended != X->P) return SPT_ESTATE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int n = 0; n < X->d; ++n) {
         if (mode != -1 && n != mode) continue;

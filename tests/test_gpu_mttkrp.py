@@ -79,6 +79,78 @@ def test_permutation_bit_exact(gpu, dims, nnz, skew):
         assert np.array_equal(k.cpu().numpy(), k_ref)
 
 
+@pytest.mark.parametrize("vdt,d,pinned,chunk", [(np.float32, 3, True, 16384),
+                                                (np.float32, 3, False, 8192),
+                                                (np.float64, 4, True, 24576)])
+def test_chunked_ingest_matches_whole(gpu, vdt, d, pinned, chunk):
+    """A tensor ingested chunk by chunk from host memory (copies on their own stream overlapping
+    the packing, first radix digit counted while packing) has the same permutations (bit-exact,
+    against the oracle) and the same deterministic MTTKRP, bit for bit, as one packed whole; a
+    ragged last chunk."""
+    import paper_1809_09175_amd as spt
+    dims = (700, 5000, 90, 40)[:d]
+    X = datagen.skewed_tensor(dims, 5 * 8192 + 1237, (1.1,) * d, seed=17)
+    X.vals = X.vals.astype(vdt)
+    T1 = _dev_tensor(X, vdt)
+    hs, hv = torch.from_numpy(X.subs), torch.from_numpy(X.vals)
+    if pinned:
+        hs, hv = hs.pin_memory(), hv.pin_memory()
+    T2 = spt.SparseTensor.from_host(hs, hv, X.dims, chunk=chunk)
+    T2.validate()
+    for T in (T1, T2):
+        T.permute()
+    torch.cuda.synchronize()
+    kind = "f64" if vdt == np.float64 else "f32"
+    dev, _ = _factors(dims, 16, seed=3, kind=kind)
+    for n in range(d):
+        p_ref, k_ref = oracle.perm(X.subs, X.dims, n)
+        for T in (T1, T2):
+            p, k = T.perm(n)
+            assert np.array_equal(p.cpu().numpy(), p_ref), n
+            assert np.array_equal(k.cpu().numpy(), k_ref), n
+        a = spt.mttkrp(T1, dev, n, algo="permuted", deterministic=True)
+        b = spt.mttkrp(T2, dev, n, algo="permuted", deterministic=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), n
+
+
+def test_chunked_ingest_errors(gpu):
+    """Appends out of order or off the 8192-entry grid are refused; calls that read the entries
+    wait for the last chunk; a bad subscript in a later chunk is reported with its global
+    index."""
+    import ctypes
+    import paper_1809_09175_amd as spt
+    from paper_1809_09175_amd import _lib
+    lib = _lib.load()
+    P = 3 * 8192 + 5
+    dims = (50, 60, 70)
+    X = datagen.skewed_tensor(dims, P, (0.0, 0.0, 0.0), seed=2)
+    X.subs[2 * 8192 + 3, 1] = 60          # out of range, in the last chunk
+    subs = torch.from_numpy(X.subs).cuda()
+    vals = torch.from_numpy(X.vals).cuda()
+    dims_arr = (ctypes.c_int64 * 3)(*dims)
+    nbytes = lib.spt_tensor_workspace_bytes(3, dims_arr, P, 1)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p()
+    assert lib.spt_tensor_create_begin(ctypes.byref(h), 3, dims_arr, P, 1,
+                                       ctypes.c_void_p(ws.data_ptr()), nbytes, None) == 0
+
+    def app(first, count):
+        return lib.spt_tensor_append(h, first, count,
+                                     ctypes.c_void_p(subs[first:].data_ptr()),
+                                     ctypes.c_void_p(vals[first:].data_ptr()), None)
+    assert app(100, 8192) == -1            # off the grid
+    assert app(0, 5000) == -1              # short chunk that does not end the tensor
+    assert app(8192, 8192) == -7           # out of order
+    assert app(0, 8192) == 0
+    assert lib.spt_tensor_permute(h, -1, None) == -7   # entries still missing
+    assert app(8192, 2 * 8192 + 5) == 0
+    bad = ctypes.c_int64()
+    assert lib.spt_tensor_validate(h, ctypes.byref(bad), None) == -2
+    assert bad.value == 2 * 8192 + 3
+    assert lib.spt_tensor_destroy(h) == 0
+
+
 def test_permutation_empty(gpu):
     X = datagen.CooTensor(np.zeros((0, 3), np.int32), np.zeros(0, np.float32), (4, 5, 6))
     T = _dev_tensor(X, np.float32)
