@@ -281,7 +281,8 @@ int spt_batch_destroy(spt_batch *B);
  * spt_mttkrp (even up to 128, multiples of 4 above), where the Cholesky factor of Gamma and its
  * inverse are formed by one workgroup and the row solves run as one FP64 product V Gamma^-1
  * (the two agree to about cond(Gamma) times the FP64 rounding unit); SPT_EUNSUPPORTED
- * otherwise.  spt_cp_gram needs ws of R x R x 8 x (1024 up to R = 64, else 64) bytes. */
+ * otherwise.  spt_cp_gram needs ws of R x R x 8 x 1024 bytes up to R = 64, at most R x R x 8 x 768
+ * above (spt_cp_workspace_bytes always suffices). */
 size_t spt_cp_workspace_bytes(const spt_tensor *X, int R);
 
 int spt_cp_gram(int64_t I, int R, const void *A, int fdtype, double *G, void *ws,

@@ -12,17 +12,26 @@ namespace spt {
 
 constexpr int kCpSmallR = 64;       // register / LDS-resident kernels up to this rank
 constexpr int kCpMaxR = 256;        // largest rank of the CP-ALS and model calls
-constexpr int kBigGramParts = 64;   // partial Grams per call above kCpSmallR (64 x R x R doubles)
+// workgroups of one Gram call above kCpSmallR (row ranges x 128 x 128 output blocks of the upper
+// triangle): about one round at three per CU; 100 MB of partials at R = 128, 134 MB at 256
+constexpr int kBigGramWgs = 768;
+constexpr int kCholB = 16;          // block size of the large-rank Cholesky factor and inverse
+constexpr int kCholMaxRp = 256;     // kCpMaxR rounded up to kCholB
 constexpr int kGramRows = 64;       // rows staged per tile in the Gram kernel
 constexpr int kMaxPartBlocks = 1024;
 constexpr int kModelMaxBlocks = 2048;  // workgroups of the model pass (fit, GCP forward)
 
 struct CpWs {
-    size_t V, Y, L, Lx, Ginv, gpart, cpart, misc, total;
+    size_t V, Y, L, Lx, Xinv, Ginv, gpart, cpart, misc, total;
 };
 
 // partial Grams one Gram call writes (each R x R doubles)
-static int gram_parts(int R) { return R <= kCpSmallR ? kMaxPartBlocks : kBigGramParts; }
+static int gram_parts(int R) {
+    if (R <= kCpSmallR) return kMaxPartBlocks;
+    const int nbk = (R + 127) / 128;  // output blocks of 128 columns (kGemmTile)
+    const int blocks = nbk * (nbk + 1) / 2;
+    return (kBigGramWgs + blocks - 1) / blocks;
+}
 
 static CpWs cp_layout(int64_t Imax, int R) {
     CpWs w;
@@ -33,9 +42,14 @@ static CpWs cp_layout(int64_t Imax, int R) {
     o += align256((size_t)Imax * R * 8);
     w.L = o;
     o += align256((size_t)R * R * 8);
-    w.Lx = o;    // above kCpSmallR: the Hadamard product, then the inverse of L
-    w.Ginv = o + (R > kCpSmallR ? align256((size_t)R * R * 8) : 0);  // and the inverse Gamma
-    o = w.Ginv + (R > kCpSmallR ? align256((size_t)R * R * 8) : 0);
+    // above kCpSmallR: W (Gamma padded to a multiple of 16, factored in place), X = L^-1, and
+    // Gamma^-1
+    const size_t rp = (size_t)(R + kCholB - 1) / kCholB * kCholB;
+    const size_t big = R > kCpSmallR ? align256(rp * rp * 8) : 0;
+    w.Lx = o;
+    w.Xinv = o + big;
+    w.Ginv = w.Xinv + big;
+    o = w.Ginv + big;
     w.gpart = o;  // Gram / column partials (R x R per block), or fit partials (2 per block)
     o += align256((size_t)std::max<size_t>((size_t)gram_parts(R) * R * R,
                                            std::max<size_t>((size_t)kMaxPartBlocks * R,
@@ -415,107 +429,266 @@ __global__ void k_norms(const double *__restrict__ sq, int R, double *__restrict
 // V Gamma^-1, then normalisation and the Gram of the stored factor in 64 x 64 output blocks.
 // ------------------------------------------------------------------------------------------
 
-// One workgroup, thread r owning row r of L (R <= 256 = kBlock).  Gamma = Hadamard product of
-// the other Grams into S; the Cholesky factor L column by column in the textbook order (row c of
-// L is broadcast through LDS before column step c; pivots <= R eps max diag raise
-// SPT_ESINGULAR); then X = L^-1 by forward substitution (thread j owns column j, written over
-// S) and Gamma^-1 = X^T X into Ginv.
+// Blocked Cholesky factor and inverse of Gamma in one workgroup, for 64 < R <= 256.  Gamma is
+// padded to Rp = 16 nb columns with the identity; W (Rp x Rp, global, L2-resident) holds the
+// Hadamard product of the other Grams and is factored in place, 16 x 16 blocks at a time:
+//   a. the diagonal block by one wavefront (lane r holds row r; row c of the factor broadcast
+//      through LDS before column step c; pivots <= R eps max diag(Gamma) raise SPT_ESINGULAR),
+//   b. the panel below it by forward substitution (a thread per row, the diagonal block in LDS),
+//   c. the trailing lower triangle minus the panel times its transpose (4 x 4 tiles per
+//      thread, the panel in LDS).
+// Then X = L^-1 (into Xg, Rp x Rp): the diagonal blocks' inverses (a thread per column), then
+// block diagonals of increasing distance d, X_ik = -X_ii sum_{k <= j < i} L_ij X_jk (the pairs
+// at one distance are independent).  Gamma^-1 = X^T X follows in k_xtx.
+
 __global__ __launch_bounds__(kBlock) void k_chol_inverse_big(const double *__restrict__ grams,
-                                                             int d, int n, int R,
-                                                             double *__restrict__ S,
-                                                             double *__restrict__ L,
-                                                             double *__restrict__ Ginv,
+                                                             int d, int n, int R, int Rp,
+                                                             double *__restrict__ W,
+                                                             double *__restrict__ Xg,
                                                              SptStatusBlock *st) {
 #pragma clang fp contract(off)
-    __shared__ double rowc[kCpMaxR];
-    __shared__ double lcc_s, maxdiag_s;
+    constexpr int B = kCholB;
+    __shared__ double Lkk[B][B + 1];
+    __shared__ double buf[(kCholMaxRp - B) * (B + 1)];  // the panel, later the T blocks
+    __shared__ double maxdiag_s;
     __shared__ int bad;
-    const int tid = threadIdx.x;
-    for (int ab = tid; ab < R * R; ab += kBlock) {
-        double g = 1.0;
-        for (int m = 0; m < d; ++m)
-            if (m != n) g *= grams[(int64_t)m * R * R + ab];
-        S[ab] = g;
-        L[ab] = 0.0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nb = Rp / B;
+    for (int ab = tid; ab < Rp * Rp; ab += kBlock) {
+        const int a = ab / Rp, b = ab - a * Rp;
+        double g;
+        if (a < R && b < R) {
+            g = 1.0;
+            for (int m = 0; m < d; ++m)
+                if (m != n) g *= grams[(int64_t)m * R * R + a * R + b];
+        } else {
+            g = (a == b) ? 1.0 : 0.0;  // identity padding
+        }
+        W[ab] = g;
+        Xg[ab] = 0.0;
     }
     __syncthreads();
     if (tid == 0) {
         double md = 0.0;
-        for (int k = 0; k < R; ++k) md = S[k * R + k] > md ? S[k * R + k] : md;
+        for (int k = 0; k < R; ++k) md = W[k * Rp + k] > md ? W[k * Rp + k] : md;
         maxdiag_s = md;
         bad = 0;
     }
     __syncthreads();
     const double tol = (double)R * 2.220446049250313e-16 * maxdiag_s;
-    const int r = tid;
-    for (int c = 0; c < R; ++c) {
-        for (int k = tid; k < c; k += kBlock) rowc[k] = L[c * R + k];
-        __syncthreads();
-        if (r == c) {
-            double piv = S[c * R + c];
-            for (int k = 0; k < c; ++k) piv -= rowc[k] * rowc[k];
-            if (!(piv > tol)) {
-                bad = 1;
-                piv = 1.0;  // keep the factor finite; the status word reports the failure
+    for (int k = 0; k < nb; ++k) {
+        const int k0 = k * B;
+        // a. diagonal block, one wavefront: lane r < B owns row r
+        if (tid < kWave) {
+            const int r = lane;
+            double row[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) row[q] = 0.0;
+            for (int c = 0; c < B; ++c) {
+                double sacc = (r < B) ? W[(k0 + r) * Rp + k0 + c] : 0.0;
+#pragma unroll
+                for (int q = 0; q < B; ++q)
+                    if (q < c) sacc -= row[q] * Lkk[c][q];
+                if (r == c) {
+                    double piv = sacc;
+                    if (k0 + c < R && !(piv > tol)) {
+                        bad = 1;
+                        piv = 1.0;  // keep the factor finite; the status word reports it
+                    }
+                    Lkk[c][c] = sqrt(piv);
+                }
+                wave_sync();
+                const double lcc = Lkk[c][c];
+                double v = 0.0;
+                if (r == c) v = lcc;
+                if (r > c && r < B) {
+                    v = sacc / lcc;
+                    Lkk[r][c] = v;
+                }
+#pragma unroll
+                for (int q = 0; q < B; ++q)
+                    if (q == c) row[q] = v;
+                wave_sync();
             }
-            lcc_s = sqrt(piv);
-            L[c * R + c] = lcc_s;
+            if (r < B)
+                for (int q = 0; q < B; ++q) W[(k0 + r) * Rp + k0 + q] = (q <= r) ? row[q] : 0.0;
         }
         __syncthreads();
-        if (r > c && r < R) {
-            double v = S[r * R + c];
-            for (int k = 0; k < c; ++k) v -= L[r * R + k] * rowc[k];
-            L[r * R + c] = v / lcc_s;
+        // b. panel: rows below the diagonal block solve z L_kk^T = w
+        const int m = Rp - k0 - B;  // rows (and columns) of the trailing matrix
+        if (tid < m) {
+            const int i = k0 + B + tid;
+            double z[B];
+#pragma unroll
+            for (int c = 0; c < B; ++c) z[c] = W[i * Rp + k0 + c];
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                double v = z[c];
+#pragma unroll
+                for (int q = 0; q < B; ++q)
+                    if (q < c) v -= z[q] * Lkk[c][q];
+                z[c] = v / Lkk[c][c];
+            }
+#pragma unroll
+            for (int c = 0; c < B; ++c) {
+                W[i * Rp + k0 + c] = z[c];
+                buf[tid * (B + 1) + c] = z[c];
+            }
+        }
+        __syncthreads();
+        // c. trailing lower triangle: W_ij -= sum_q P_iq P_jq, 4 x 4 tiles per thread
+        const int mt = (m + 3) / 4;
+        for (int t = tid; t < mt * mt; t += kBlock) {
+            const int ti = t / mt, tj = t - ti * mt;
+            if (tj > ti) continue;
+            double acc[4][4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                double a[4], b[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    const int ii = ti * 4 + x, jj = tj * 4 + x;
+                    a[x] = ii < m ? buf[ii * (B + 1) + q] : 0.0;
+                    b[x] = jj < m ? buf[jj * (B + 1) + q] : 0.0;
+                }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    const int ii = ti * 4 + x, jj = tj * 4 + y;
+                    if (ii < m && jj < m && jj <= ii)
+                        W[(k0 + B + ii) * Rp + k0 + B + jj] -= acc[x][y];
+                }
         }
         __syncthreads();
     }
-    // X = L^-1 (lower triangular), column j by thread j, over S
-    if (r < R) {
-        const int j = r;
-        for (int i = 0; i < j; ++i) S[i * R + j] = 0.0;
-        for (int i = j; i < R; ++i) {
-            double v = (i == j) ? 1.0 : 0.0;
-            for (int k = j; k < i; ++k) v -= L[i * R + k] * S[k * R + j];
-            S[i * R + j] = v / L[i * R + i];
+    // X = L^-1.  Diagonal blocks first: thread t inverts column t % B of block t / B.
+    {
+        const int k = tid / B, c = tid % B;
+        if (k < nb) {
+            const int k0 = k * B;
+            double x[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+                for (int q = 0; q < B; ++q)
+                    if (q >= c && q < i) v -= W[(k0 + i) * Rp + k0 + q] * x[q];
+                x[i] = (i < c) ? 0.0 : v / W[(k0 + i) * Rp + k0 + i];
+            }
+#pragma unroll
+            for (int i = 0; i < B; ++i) Xg[(k0 + i) * Rp + k0 + c] = x[i];
         }
     }
     __syncthreads();
-    // Gamma^-1 = X^T X: entry (i, j) sums X[k][i] X[k][j] over k >= max(i, j)
-    if (r < R) {
-        const int j = r;
-        for (int i = 0; i < R; ++i) {
+    // then the blocks at distance dist below the diagonal, all pairs of one distance at once
+    for (int dist = 1; dist < nb; ++dist) {
+        const int npairs = nb - dist;
+        // T_ik = sum_{j = k .. i-1} L_ij X_jk into buf (pair p = k)
+        for (int e = tid; e < npairs * B * B; e += kBlock) {
+            const int k = e / (B * B), rc = e - k * B * B, r = rc / B, c = rc - r * B;
+            const int i = k + dist;
             double v = 0.0;
-            for (int k = (i > j ? i : j); k < R; ++k) v += S[k * R + i] * S[k * R + j];
-            Ginv[i * R + j] = v;
+            for (int j = k; j < i; ++j)
+                for (int q = 0; q < B; ++q)
+                    v += W[(i * B + r) * Rp + j * B + q] * Xg[(j * B + q) * Rp + k * B + c];
+            buf[e] = v;
         }
+        __syncthreads();
+        // X_ik = -X_ii T_ik (X_ii lower triangular)
+        for (int e = tid; e < npairs * B * B; e += kBlock) {
+            const int k = e / (B * B), rc = e - k * B * B, r = rc / B, c = rc - r * B;
+            const int i = k + dist;
+            double v = 0.0;
+            for (int q = 0; q <= r; ++q)
+                v += Xg[(i * B + r) * Rp + i * B + q] * buf[k * B * B + q * B + c];
+            Xg[(i * B + r) * Rp + k * B + c] = -v;
+        }
+        __syncthreads();
     }
     if (tid == 0 && bad) raise_status(st, SPT_ESINGULAR);
 }
 
-// Y = V Gamma^-1 (I x R times R x R, FP64 products and sums): 64 x 64 output tiles, the
-// reduction dimension in steps of 16 staged through LDS, 4 x 4 outputs per thread.
-constexpr int kGemmTile = 64, kGemmK = 16;
+// Gamma^-1 = X^T X for the lower triangular X = L^-1 (Rp x Rp; rows past R are zero in the
+// first R columns): 64 x 64 output tiles, the sum over rows in steps of 16 through LDS.
+constexpr int kXtxTile = 64, kXtxK = 16;
 
-template <class VT>
-__global__ __launch_bounds__(kBlock) void k_solve_gemm(const VT *__restrict__ V, int64_t I,
-                                                       int R, const double *__restrict__ Ginv,
-                                                       double *__restrict__ Y) {
-    __shared__ double As[kGemmTile][kGemmK + 1];
-    __shared__ double Bs[kGemmK][kGemmTile + 1];
+__global__ __launch_bounds__(kBlock) void k_xtx(const double *__restrict__ Xg, int Rp, int R,
+                                                double *__restrict__ Ginv) {
+    __shared__ double As[kXtxK][kXtxTile + 1];
+    __shared__ double Bs[kXtxK][kXtxTile + 1];
     const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
-    const int64_t r0 = (int64_t)blockIdx.x * kGemmTile;
-    const int c0 = blockIdx.y * kGemmTile;
+    const int a0 = blockIdx.x * kXtxTile, b0 = blockIdx.y * kXtxTile;
     double acc[4][4];
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    const int t0 = (a0 > b0 ? a0 : b0) / kXtxK * kXtxK;  // X[t][a] = 0 below t < a
+    for (int t = t0; t < Rp; t += kXtxK) {
+        for (int e = tid; e < kXtxK * kXtxTile; e += kBlock) {
+            const int tt = e / kXtxTile, cc = e - tt * kXtxTile;
+            As[tt][cc] = (a0 + cc < Rp) ? Xg[(t + tt) * Rp + a0 + cc] : 0.0;
+            Bs[tt][cc] = (b0 + cc < Rp) ? Xg[(t + tt) * Rp + b0 + cc] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tt = 0; tt < kXtxK; ++tt) {
+            double a[4], b[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) a[x] = As[tt][tr * 4 + x];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) b[y] = Bs[tt][tc * 4 + y];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int a = a0 + tr * 4 + x, b = b0 + tc * 4 + y;
+            if (a < R && b < R) Ginv[a * R + b] = acc[x][y];
+        }
+}
+
+// Y = V Gamma^-1 (I x R times R x R, FP64 products and sums): 128 x 128 output tiles, the
+// reduction dimension in steps of 16 staged through LDS (transposed, so a thread's eight rows
+// and eight columns are contiguous), 8 x 8 outputs per thread (64 FMAs per 16 LDS values).
+constexpr int kGemmTile = 128, kGemmK = 16, kGemmSub = 8;
+
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_solve_gemm(const VT *__restrict__ V, int64_t I,
+                                                       int R, const double *__restrict__ Ginv,
+                                                       double *__restrict__ Y) {
+    __shared__ double As[kGemmK][kGemmTile];  // As[k][row]
+    __shared__ double Bs[kGemmK][kGemmTile];  // Bs[k][col]
+    const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+    const int64_t r0 = (int64_t)blockIdx.x * kGemmTile;
+    const int c0 = blockIdx.y * kGemmTile;
+    double acc[kGemmSub][kGemmSub];
+#pragma unroll
+    for (int x = 0; x < kGemmSub; ++x)
+#pragma unroll
+        for (int y = 0; y < kGemmSub; ++y) acc[x][y] = 0.0;
     for (int k0 = 0; k0 < R; k0 += kGemmK) {
         for (int e = tid; e < kGemmTile * kGemmK; e += kBlock) {
-            const int rr = e / kGemmK, kk = e - rr * kGemmK;
+            const int rr = e / kGemmK, kk = e - rr * kGemmK;  // consecutive k along a row of V
             const int64_t row = r0 + rr;
             const int k = k0 + kk;
-            As[rr][kk] = (row < I && k < R) ? (double)V[row * R + k] : 0.0;
+            As[kk][rr] = (row < I && k < R) ? (double)V[row * R + k] : 0.0;
         }
         for (int e = tid; e < kGemmK * kGemmTile; e += kBlock) {
             const int kk = e / kGemmTile, cc = e - kk * kGemmTile;
@@ -525,25 +698,25 @@ __global__ __launch_bounds__(kBlock) void k_solve_gemm(const VT *__restrict__ V,
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kGemmK; ++kk) {
-            double a[4], b[4];
+            double a[kGemmSub], b[kGemmSub];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) a[x] = As[tr * 4 + x][kk];
+            for (int x = 0; x < kGemmSub; ++x) a[x] = As[kk][tr * kGemmSub + x];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) b[y] = Bs[kk][tc * 4 + y];
+            for (int y = 0; y < kGemmSub; ++y) b[y] = Bs[kk][tc * kGemmSub + y];
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < kGemmSub; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+                for (int y = 0; y < kGemmSub; ++y) acc[x][y] += a[x] * b[y];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        const int64_t row = r0 + tr * 4 + x;
+    for (int x = 0; x < kGemmSub; ++x) {
+        const int64_t row = r0 + tr * kGemmSub + x;
         if (row >= I) continue;
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int c = c0 + tc * 4 + y;
+        for (int y = 0; y < kGemmSub; ++y) {
+            const int c = c0 + tc * kGemmSub + y;
             if (c < R) Y[row * R + c] = acc[x][y];
         }
     }
@@ -564,28 +737,34 @@ __global__ __launch_bounds__(kBlock) void k_normalize_store(const double *__rest
     }
 }
 
-// Partial Gram A^T A for one 64 x 64 output block (blockIdx.y = block row * nbk + block column)
-// over a range of rows (blockIdx.x of gridDim.x): rows staged 32 at a time in LDS, 4 x 4 outputs
-// per thread, each entry summing its rows in increasing order.
-constexpr int kBigGramRows = 32;
+// Partial Gram A^T A for one 128 x 128 output block (bi, bj) with bi <= bj (blockIdx.y indexes
+// the upper block triangle row by row) over a range of rows (blockIdx.x of gridDim.x): rows
+// staged 16 at a time in LDS, 8 x 8 outputs per thread, each entry summing its rows in
+// increasing order.  An off-diagonal block is written to both (a, b) and (b, a).
+constexpr int kBigGramRows = 16;
 
 template <class FT>
 __global__ __launch_bounds__(kBlock) void k_gram_big_partial(const FT *__restrict__ A, int64_t I,
                                                              int R, double *__restrict__ gpart) {
-    __shared__ double Ta[kBigGramRows][kGemmTile + 1];
-    __shared__ double Tb[kBigGramRows][kGemmTile + 1];
+    __shared__ double Ta[kBigGramRows][kGemmTile];
+    __shared__ double Tb[kBigGramRows][kGemmTile];
     const int tid = threadIdx.x, ta = tid / 16, tb = tid % 16;
     const int nbk = (R + kGemmTile - 1) / kGemmTile;
-    const int bi = blockIdx.y / nbk, bj = blockIdx.y - bi * nbk;
+    int bi = 0, rem = blockIdx.y;
+    while (rem >= nbk - bi) {  // blockIdx.y -> (bi, bj), bj >= bi
+        rem -= nbk - bi;
+        ++bi;
+    }
+    const int bj = bi + rem;
     const int ca = bi * kGemmTile, cb = bj * kGemmTile;
     const int64_t per = ceil_div(ceil_div(I, (int64_t)gridDim.x), (int64_t)kBigGramRows) * kBigGramRows;
     const int64_t rbeg = (int64_t)blockIdx.x * per;
     const int64_t rend = (rbeg + per < I) ? rbeg + per : I;
-    double acc[4][4];
+    double acc[kGemmSub][kGemmSub];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < kGemmSub; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+        for (int y = 0; y < kGemmSub; ++y) acc[x][y] = 0.0;
     for (int64_t r0 = rbeg; r0 < rend; r0 += kBigGramRows) {
         for (int e = tid; e < kBigGramRows * kGemmTile; e += kBlock) {
             const int rr = e / kGemmTile, cc = e - rr * kGemmTile;
@@ -595,26 +774,30 @@ __global__ __launch_bounds__(kBlock) void k_gram_big_partial(const FT *__restric
             Tb[rr][cc] = (ok && cb + cc < R) ? load_f64<FT>(A + row * R + cb + cc) : 0.0;
         }
         __syncthreads();
+#pragma unroll 4
         for (int rr = 0; rr < kBigGramRows; ++rr) {
-            double a[4], b[4];
+            double a[kGemmSub], b[kGemmSub];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) a[x] = Ta[rr][ta * 4 + x];
+            for (int x = 0; x < kGemmSub; ++x) a[x] = Ta[rr][ta * kGemmSub + x];
 #pragma unroll
-            for (int y = 0; y < 4; ++y) b[y] = Tb[rr][tb * 4 + y];
+            for (int y = 0; y < kGemmSub; ++y) b[y] = Tb[rr][tb * kGemmSub + y];
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < kGemmSub; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+                for (int y = 0; y < kGemmSub; ++y) acc[x][y] += a[x] * b[y];
         }
         __syncthreads();
     }
     double *out = gpart + (int64_t)blockIdx.x * R * R;
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < kGemmSub; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            const int a = ca + ta * 4 + x, b = cb + tb * 4 + y;
-            if (a < R && b < R) out[a * R + b] = acc[x][y];
+        for (int y = 0; y < kGemmSub; ++y) {
+            const int a = ca + ta * kGemmSub + x, b = cb + tb * kGemmSub + y;
+            if (a < R && b < R) {
+                out[a * R + b] = acc[x][y];
+                if (bi != bj) out[b * R + a] = acc[x][y];
+            }
         }
 }
 
@@ -965,10 +1148,11 @@ static int launch_gram_big(const FT *A, const double *Y, const double *lambda, F
         A = Aout;
     }
     const int nbk = (R + kGemmTile - 1) / kGemmTile;
-    const int parts = (int)std::min<int64_t>(kBigGramParts,
+    const int parts = (int)std::min<int64_t>(gram_parts(R),
                                              std::max<int64_t>(1, ceil_div(I, kBigGramRows)));
-    hipLaunchKernelGGL((k_gram_big_partial<FT>), dim3((unsigned)parts, (unsigned)(nbk * nbk)),
-                       dim3(kBlock), 0, s, A, I, R, gpart);
+    hipLaunchKernelGGL((k_gram_big_partial<FT>),
+                       dim3((unsigned)parts, (unsigned)(nbk * (nbk + 1) / 2)), dim3(kBlock), 0, s,
+                       A, I, R, gpart);
     hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)ceil_div(R * R, kBlock / kWave)), dim3(kBlock), 0,
                        s, gpart, parts, R * R, G);
     return hipGetLastError() == hipSuccess ? SPT_OK : SPT_EHIP;
@@ -1142,10 +1326,14 @@ int spt_cp_als_mode(spt_tensor *X, int mode, int R, void *const *factors, int fd
     if (rc) return rc;
     if (R > kCpSmallR) {
         // Gamma, L and Gamma^-1 in one workgroup; the row solves as one GEMM V Gamma^-1
-        double *Sx = reinterpret_cast<double *>(w + L.Lx);
+        double *Wf = reinterpret_cast<double *>(w + L.Lx);
+        double *Xi = reinterpret_cast<double *>(w + L.Xinv);
         double *Gi = reinterpret_cast<double *>(w + L.Ginv);
+        const int Rp = (R + kCholB - 1) / kCholB * kCholB;
         hipLaunchKernelGGL(k_chol_inverse_big, dim3(1), dim3(kBlock), 0, s, grams, X->d, mode, R,
-                           Sx, Lf, Gi, X->status);
+                           Rp, Wf, Xi, X->status);
+        const unsigned nt = (unsigned)ceil_div(R, kXtxTile);
+        hipLaunchKernelGGL(k_xtx, dim3(nt, nt), dim3(kBlock), 0, s, Xi, Rp, R, Gi);
         const dim3 g((unsigned)ceil_div(I, (int64_t)kGemmTile), (unsigned)ceil_div(R, kGemmTile));
         if (fdtype == SPT_F64)
             hipLaunchKernelGGL((k_solve_gemm<double>), g, dim3(kBlock), 0, s,

@@ -37,6 +37,24 @@ __global__ __launch_bounds__(kBlock) void k_pack_tiles(const int32_t *__restrict
     int64_t bad_min = INT64_MAX;
     for (int sub = 0; sub < kSortSubs; ++sub) {
         const int64_t base = tile * kSortTile + (int64_t)sub * kSortSub;
+        // every item's loads first (kSortItems entries per thread in flight), then the packing
+        // and the digit counts
+        int32_t l[kSortItems][SPT_MAX_ORDER];
+        VT v[kSortItems];
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t e = base + it * kBlock + tid;
+            const int64_t i = e - first;  // position in the caller's chunk
+#pragma unroll
+            for (int m = 0; m < SPT_MAX_ORDER; ++m) l[it][m] = 0;
+            v[it] = 0;
+            if (e < P) {
+#pragma unroll
+                for (int m = 0; m < SPT_MAX_ORDER; ++m)
+                    if (m < d) l[it][m] = subs[i * d + m];
+                v[it] = vals[i];
+            }
+        }
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             const int64_t e = base + it * kBlock + tid;
@@ -45,25 +63,23 @@ __global__ __launch_bounds__(kBlock) void k_pack_tiles(const int32_t *__restrict
 #pragma unroll
             for (int k = 0; k < RW; ++k) w[k] = 0;
             if (valid) {
-                const int64_t i = e - first;  // position in the caller's chunk
 #pragma unroll
                 for (int m = 0; m < SPT_MAX_ORDER; ++m) {
                     if (m < d) {
-                        int32_t l = subs[i * d + m];
-                        if (l < 0 || (int64_t)l >= dims[m]) {
+                        int32_t lm = l[it][m];
+                        if (lm < 0 || (int64_t)lm >= dims[m]) {
                             bad_min = e < bad_min ? e : bad_min;
-                            l = 0;  // keep every later access in bounds
+                            lm = 0;  // keep every later access in bounds
                         }
-                        w[m] = l;
+                        w[m] = lm;
                     }
                 }
-                const VT v = vals[i];
                 if constexpr (sizeof(VT) == 8) {
-                    const uint64_t b = __double_as_longlong(v);
+                    const uint64_t b = __double_as_longlong(v[it]);
                     w[RW - 2] = (int32_t)(uint32_t)b;
                     w[RW - 1] = (int32_t)(uint32_t)(b >> 32);
                 } else {
-                    w[RW - 1] = __float_as_int(v);
+                    w[RW - 1] = __float_as_int(v[it]);
                 }
                 int4 *out = rec + e * (RW / 4);
                 out[0] = make_int4(w[0], w[1], w[2], w[3]);
