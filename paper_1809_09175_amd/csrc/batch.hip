@@ -79,10 +79,11 @@ __device__ __forceinline__ void batch_unit(int4 *smem4, const BatchItem &it, int
 }
 
 // ATOMIC = false compiles the permuted configurations only: the atomic path's tile sort raises
-// the kernel's register demand (which every configuration then pays, in spills), so a batch
-// whose products are all permuted runs the lighter kernel.
+// the kernel's register demand, so a batch whose products are all permuted runs the lighter
+// kernel (4 waves per SIMD); with the atomic path the kernel may take 2 waves per SIMD's
+// registers instead of spilling.
 template <class FT, bool ATOMIC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_mttkrp_batched(const BatchItem *__restrict__ items,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ATOMIC ? 2 : 4, 8))) void k_mttkrp_batched(const BatchItem *__restrict__ items,
                                                            int nitems, int64_t total_units,
                                                            unsigned long long *counter) {
     extern __shared__ int4 smem4[];
