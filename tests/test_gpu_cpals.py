@@ -123,13 +123,13 @@ def test_cp_mode_update_low_precision(gpu, kind):
             assert np.array_equal(st.factors[n].cpu().numpy(), a.astype(np.float32)), n
 
 
-@pytest.mark.parametrize("R", [5, 20, 40, 64, 96, 128, 200, 256])
+@pytest.mark.parametrize("R", [5, 20, 40, 64, 96, 98, 128, 200, 256])
 def test_cp_mode_update_fp64_ranks(gpu, R):
     """FP64 mode updates at ranks off the 16/32/64 grid (padded Cholesky, solve and Gram tiles),
-    at 64 (the largest of the one-wavefront Cholesky) and above it up to 256 (Cholesky and
-    inverse in one workgroup, the row solves as one product with the inverse, 64 x 64 Gram
-    blocks, partial last blocks at 96 and 200), against the oracle's mode update from the same
-    state."""
+    at 64 (the largest of the one-wavefront Cholesky) and above it up to 256 (blocked Cholesky
+    and inverse in one workgroup, Gamma padded to a multiple of 16 at 98 and 200; the row solves
+    as one product with the inverse and the Gram in 128 x 128 tiles, partial at 96, 98 and 200),
+    against the oracle's mode update from the same state."""
     import paper_1809_09175_amd as spt
     X = _skewed4_small()
     X.vals = X.vals.astype(np.float64)
@@ -279,7 +279,7 @@ def test_fit_rank_one_many_entries(gpu):
     assert abs(st.fit(source="mttkrp") - f_ref) < 1e-11
 
 
-@pytest.mark.parametrize("R", [24, 96, 128, 256])
+@pytest.mark.parametrize("R", [24, 96, 98, 128, 200, 256])
 def test_model_values(gpu, R):
     """Model values of every stored entry, including the wide lane layouts above 64 columns."""
     import paper_1809_09175_amd as spt
@@ -472,14 +472,42 @@ def test_gcp_general_losses(gpu, loss, kind, copies):
 
 # ----------------------------------------------------------------------- fused GCP passes
 
-def _fused_case(dt, d, P, seed):
+def _fused_case(dt, d, P, seed, R=6):
     dims = (60, 45, 30, 20)[:d]
     rng = np.random.default_rng(seed)
     lin = rng.choice(int(np.prod(dims)), size=P, replace=False)
     subs = np.stack(np.unravel_index(lin, dims), axis=1).astype(np.int32)
     vals = rng.poisson(1.0, size=P).astype(dt)
-    A = [(rng.random((I, 6)) * 0.6 + 0.02).astype(dt) for I in dims]
+    scale = 0.6 * (6.0 / R) ** (1.0 / d)   # keeps the model values of order one at any rank
+    A = [(rng.random((I, R)) * scale + 0.02 * scale).astype(dt) for I in dims]
     return subs, vals, dims, A
+
+
+@pytest.mark.parametrize("R", [96, 128, 256])
+@pytest.mark.parametrize("kind", ["f64", "f32"])
+def test_gcp_fused_and_unfused_large_rank(gpu, kind, R):
+    """Poisson GCP loss and gradients above 64 columns (wide lane layouts of the fused passes
+    and of the unfused model pass) against the FP64 oracle, fused against unfused."""
+    import paper_1809_09175_amd as spt
+    dt = np.float64 if kind == "f64" else np.float32
+    subs, vals, dims, A = _fused_case(dt, 3, 5003, seed=R, R=R)
+    T = spt.SparseTensor(torch.from_numpy(subs).cuda(), torch.from_numpy(vals).cuda(), dims)
+    T.permute()
+    T.sort_copy()
+    L_ref, g_ref = oracle.gcp(subs, vals, dims, [a.astype(np.float64) for a in A], "poisson")
+    tol, gtol = (1e-12, 1e-12) if kind == "f64" else (1e-5, 1e-4)
+    for fused in (True, False):
+        spt.GCPLoss.use_fused = fused
+        try:
+            facs = [torch.from_numpy(a).cuda().requires_grad_(True) for a in A]
+            L = spt.GCPLoss.apply(T, None, "poisson", *facs)
+            L.backward()
+            torch.cuda.synchronize()
+        finally:
+            spt.GCPLoss.use_fused = True
+        assert abs(L.item() - L_ref) < tol * abs(L_ref), (fused, L.item(), L_ref)
+        for n in range(3):
+            assert _relerr(facs[n].grad.cpu().numpy(), g_ref[n]) < gtol, (fused, n)
 
 
 @pytest.mark.parametrize("loss", ["poisson", "bernoulli", "gaussian", "gamma"])
