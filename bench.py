@@ -726,6 +726,13 @@ def main():
         extras["sort_and_copy_over_cp_als_iteration"] = round((sort_ms + copy_ms) / iter_ms, 3)
         log(f"CP-ALS sweep {sweep_ms:.2f} ms, fit {fit_ms:.2f} ms (from the MTTKRP {fast_fit_ms:.2f} ms)")
         del st
+        # the rank of the paper's CP-ALS experiment (Sec. 7.1): R = 128, FP32 factors
+        st = spt.CPState(T, factors_for(128))
+        st.sweep()
+        torch.cuda.synchronize()
+        extras["cp_als_sweep_ms_R128"] = round(timed(lambda: st.sweep(), reps=2), 3)
+        log(f"CP-ALS sweep at R = 128: {extras['cp_als_sweep_ms_R128']:.2f} ms")
+        del st
         # STREAM-style triad on 3 x 1 GiB
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device=dev)
