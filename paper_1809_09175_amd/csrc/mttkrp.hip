@@ -62,14 +62,17 @@ static int pow2_at_least(int x) {
 
 // Default lane layout, from measurements on MI355X (1e8-entry Zipf tensor, R = 16/32/64, each
 // layout at its best unroll): the permuted kernel is fastest with 16 x 1, 8 x 4 and 16 x 4
-// (lanes x FP32 columns) at R = 16, 32, 64, and with 16 x 1, 16 x 2, 32 x 2 for BF16 factors;
-// i.e. one column per lane below 32 FP32 columns, then four (BF16: one up to 16, then two),
-// over as many lanes as cover R.  The atomic kernel is fastest with one column per lane (its LDS
+// (lanes x FP32 columns) at R = 16, 32, 64, and with 8 x 2, 16 x 2 and 8 x 8 for BF16 factors
+// (2.65, 2.90 and 4.47 ms for three modes, against 2.75-2.85, 2.92 and 4.82 with 16 x 1,
+// 16 x 2 and 32 x 2); i.e. one FP32 column per lane below 32 columns, then four; BF16 one column
+// below 16, two up to 32, eight up to 64 (sixteen bytes per lane), two above; over as many
+// lanes as cover R.  The atomic kernel is fastest with one column per lane (its LDS
 // and global atomics are per column either way).  Columns per lane must divide R.
 static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out) {
     int cpl = 1, G = 8;
     if (algo == SPT_ALGO_PERMUTED) {
-        int c = (fdtype == SPT_BF16) ? (R <= 16 ? 1 : 2) : (R < 32 ? 1 : (R <= 64 ? 4 : 8));
+        int c = (fdtype == SPT_BF16) ? (R < 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 8 : 2)))
+                                     : (R < 32 ? 1 : (R <= 64 ? 4 : 8));
         while (c > 1 && R % c != 0) c >>= 1;
         int g = pow2_at_least((R + c - 1) / c);
         if (g < 8) g = 8;
