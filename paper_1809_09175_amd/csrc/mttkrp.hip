@@ -65,17 +65,20 @@ static int pow2_at_least(int x) {
 // (lanes x FP32 columns) at R = 16, 32, 64, and with 8 x 2, 16 x 2 and 8 x 8 for BF16 factors
 // (2.65, 2.90 and 4.47 ms for three modes, against 2.75-2.85, 2.92 and 4.82 with 16 x 1,
 // 16 x 2 and 32 x 2); i.e. one FP32 column per lane below 32 columns, then four; BF16 one column
-// below 16, two up to 32, eight up to 64 (sixteen bytes per lane), two above; over as many
-// lanes as cover R.  The atomic kernel is fastest with one column per lane (its LDS
+// below 16, two up to 32, eight up to 64 (sixteen bytes per lane), two above; FP64 four
+// columns per lane from R = 16 (4 x 4, 8 x 4, 16 x 4: 4.53, 7.30, 13.8 ms against 7.84, 7.61,
+// 14.6 with 16 x 1 and the FP32 chunk rules); over as many lanes as cover R.  The atomic kernel is fastest with one column per lane (its LDS
 // and global atomics are per column either way).  Columns per lane must divide R.
 static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out) {
     int cpl = 1, G = 8;
     if (algo == SPT_ALGO_PERMUTED) {
-        int c = (fdtype == SPT_BF16) ? (R < 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 8 : 2)))
-                                     : (R < 32 ? 1 : (R <= 64 ? 4 : 8));
+        int c = (fdtype == SPT_BF16)  ? (R < 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 8 : 2)))
+                : (fdtype == SPT_F64) ? (R < 16 ? 1 : (R <= 64 ? 4 : 8))
+                                      : (R < 32 ? 1 : (R <= 64 ? 4 : 8));
         while (c > 1 && R % c != 0) c >>= 1;
         int g = pow2_at_least((R + c - 1) / c);
-        if (g < 8) g = 8;
+        const int gmin = (fdtype == SPT_F64 && c == 4) ? 4 : 8;
+        if (g < gmin) g = gmin;
         if (cfg_supported(g, c)) {
             *G_out = g;
             *cpl_out = c;
@@ -141,7 +144,8 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
         // wavefronts to occupy the GPU: aim for at least ~2048 wave chunks (the permuted launch
         // may then match the chunk to the device's resident wavefronts: capacity_chunk)
         t.flags |= kTuneChunkDefaulted;
-        const int64_t cap = (lalgo == SPT_ALGO_PERMUTED) ? 4096 : 2048;
+        const int64_t cap = (lalgo != SPT_ALGO_PERMUTED) ? 2048
+                            : (fdtype == SPT_F64 && R <= 32) ? 8192 : 4096;
         int64_t c = (X->P / 2048) & ~int64_t(63);
         t.nnz_per_wave = (int)(c < 256 ? 256 : (c > cap ? cap : c));
     }

@@ -1113,8 +1113,11 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
     if (grid == 0) return SPT_OK;
     if (a.algo == SPT_ALGO_PERMUTED || a.algo == SPT_ALGO_PERMUTED_COPY) {
         int chunk = a.chunk;
-        if (a.auto_chunk && a.slot_keys == nullptr && a.srec != nullptr && CPL >= 4) {
-            // resident wavefronts of this instantiation on the whole device (queried once)
+        if (a.auto_chunk && a.slot_keys == nullptr && a.srec != nullptr && CPL >= 4 &&
+            sizeof(FT) <= 4) {
+            // resident wavefronts of this instantiation on the whole device (queried once);
+            // FP64 factors keep the default chunk (8192-entry chunks ran 4% faster at R = 32
+            // than the matched 24-32k ones)
             static const int per_cu = [] {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
