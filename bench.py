@@ -679,11 +679,14 @@ def main():
             pc = measure(r, "permuted_copy", 5, 1)
             p = measure(r, "permuted", 5, 1)
             a = measure(r, "atomic", 3, 1)
+            b = measure(r, "permuted_copy", 5, 2, A=[spt.to_bf16(x) for x in factors_for(r)])
             per_rank[str(r)] = {"permuted_copy_gbs": round(pc["gbs"], 1),
                                 "permuted_gbs": round(p["gbs"], 1), "atomic_gbs": round(a["gbs"], 1),
                                 "permuted_copy_ms": round(pc["ms_per_step"], 3),
                                 "permuted_ms": round(p["ms_per_step"], 3),
-                                "atomic_ms": round(a["ms_per_step"], 3)}
+                                "atomic_ms": round(a["ms_per_step"], 3),
+                                "bf16_permuted_copy_ms": round(b["ms_per_step"], 3),
+                                "bf16_speedup": round(pc["ms_per_step"] / b["ms_per_step"], 3)}
             log(f"R={r}: permuted copy {pc['gbs']:.0f}, gather {p['gbs']:.0f}, atomic {a['gbs']:.0f} GB/s")
         # BF16 factors on the same tensor
         A32 = factors_for(R)
@@ -694,6 +697,9 @@ def main():
             "ms_per_step": round(b16["ms_per_step"], 3),
             "speedup_vs_fp32": round(main_res["ms_per_step"] / b16["ms_per_step"], 3)}
         log(f"BF16 factors: {b16['ms_per_step']:.3f} ms/step")
+        if str(R) in per_rank:
+            per_rank[str(R)]["bf16_permuted_copy_ms"] = round(b16["ms_per_step"], 3)
+            per_rank[str(R)]["bf16_speedup"] = extras["bf16_factors_same_tensor"]["speedup_vs_fp32"]
         # one CP-ALS sweep (FP32 factors, permuted MTTKRP) and the fit
         st = spt.CPState(T, factors_for(R))
         st.sweep()
