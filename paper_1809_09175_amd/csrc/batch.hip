@@ -63,6 +63,8 @@ __device__ __forceinline__ void batch_unit(int4 *smem4, const BatchItem &it, int
     float *V = static_cast<float *>(it.V);
     if constexpr (ALGO == SPT_ALGO_PERMUTED) {
         using SM = PermShared<D, G, CPL, float, float>;
+        static_assert(sizeof(SM) == perm_shared_bytes(G, CPL, SM::RQ, 4),
+                      "the dynamic LDS is sized with perm_shared_bytes");
         SM *sm = reinterpret_cast<SM *>(smem4);
         const int wave = threadIdx.x >> 6;
         const int64_t c0 = bc0 + (int64_t)wave * it.chunk;

@@ -844,7 +844,8 @@ __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, 
                                                   double *__restrict__ part, int chunk, int loss) {
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int U = UnrollFor<KERNEL_MODEL, G, CPL, FT>::value;
-    __shared__ int4 s_rec[kBlock / kWave][kWave * RQ];
+    constexpr int GS = staged_group_stride(G, RQ);
+    __shared__ int4 s_rec[kBlock / kWave][(kWave / G) * GS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane / G, gl = lane % G;
     const int col0 = gl * CPL;
@@ -868,8 +869,8 @@ __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, 
                 const int4 *r = rec + (c0 + b + lane) * RQ;
                 // streamed once: non-temporal, as in the permuted MTTKRP (fit 1.83 ms instead
                 // of 1.89 on 1e8 entries at R = 32)
-                s_rec[wave][lane * RQ] = load_stream(r);
-                if constexpr (RQ == 2) s_rec[wave][lane * RQ + 1] = load_stream(r + 1);
+                s_rec[wave][g * GS + gl * RQ] = load_stream(r);
+                if constexpr (RQ == 2) s_rec[wave][g * GS + gl * RQ + 1] = load_stream(r + 1);
             }
             wave_sync();
             int cnt = len - b - g * G;
@@ -880,7 +881,7 @@ __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, 
                 if (u0 + U <= cnt) {  // whole unroll: straight-line code, all gathers in flight
 #pragma unroll
                     for (int u = 0; u < U; ++u)
-                        model_entry<D, RW, RQ, CPL, FT, VT, CT>(&s_rec[wave][(g * G + u0 + u) * RQ], A,
+                        model_entry<D, RW, RQ, CPL, FT, VT, CT>(&s_rec[wave][g * GS + (u0 + u) * RQ], A,
                                                                 rowbytes, colbytes, colok, lam, t[u], x[u]);
                 } else {
 #pragma unroll
@@ -888,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_model(const int4 *__restrict__ rec, 
                         t[u] = 0;
                         x[u] = 0;
                         if (u0 + u < cnt)
-                            model_entry<D, RW, RQ, CPL, FT, VT, CT>(&s_rec[wave][(g * G + u0 + u) * RQ], A,
+                            model_entry<D, RW, RQ, CPL, FT, VT, CT>(&s_rec[wave][g * GS + (u0 + u) * RQ], A,
                                                                     rowbytes, colbytes, colok, lam, t[u],
                                                                     x[u]);
                     }

@@ -156,8 +156,9 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
         // the whole output must fit one workgroup's LDS next to the record staging buffer,
         // within 64 KiB so two workgroups share a CU
         const size_t at = (fdtype == SPT_F64) ? 8 : 4;
-        const size_t need = (size_t)(kBlock / kWave) * kWave * (X->rec_words / 4) * 16 +
-                            (size_t)X->dims[mode] * G * cpl * at;
+        const size_t need =
+            (size_t)(kBlock / kWave) * (kWave / G) * staged_group_stride(G, X->rec_words / 4) * 16 +
+            (size_t)X->dims[mode] * G * cpl * at;
         if (need > kPrivatizedLds) return SPT_EUNSUPPORTED;
     }
     t.lanes_per_nnz = G;

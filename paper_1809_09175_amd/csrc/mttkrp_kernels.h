@@ -341,11 +341,19 @@ struct UnrollFor {
     static constexpr int value = unroll_for(KERNEL, G, CPL, (int)sizeof(FT));
 };
 
+// Staged records of one lane group in LDS: its G records plus one 16-byte pad.  The lanes of a
+// group read the same record at a time while the groups read records G records apart; without
+// the pad those addresses are a multiple of 128 bytes apart for G >= 8, so every group hits the
+// same LDS banks (an 8-way conflict at 8 x 4, counted as 1.25e8 conflict cycles per launch on
+// the 1e8-entry power-law tensor).  With it, group g starts 4g banks further on.  The kernels
+// measured no faster for it: the conflicts overlapped the wait for the factor-row gathers.
+__host__ __device__ constexpr int staged_group_stride(int G, int RQ) { return G * RQ + 1; }
+
 // Bytes of one wavefront's PermShared (the batched kernel sizes its dynamic LDS with it).
-inline size_t perm_shared_bytes(int G, int CPL, int RQ, int at_bytes) {
+constexpr size_t perm_shared_bytes(int G, int CPL, int RQ, int at_bytes) {
     const int NG = kWave / G;
-    const size_t b = (size_t)kWave * RQ * 16 + (size_t)2 * NG * G * CPL * at_bytes +
-                     (size_t)2 * NG * 4;
+    const size_t b = (size_t)NG * staged_group_stride(G, RQ) * 16 +
+                     (size_t)2 * NG * G * CPL * at_bytes + (size_t)2 * NG * 4;
     return (b + 15) / 16 * 16;
 }
 
@@ -354,7 +362,7 @@ inline size_t perm_shared_bytes(int G, int CPL, int RQ, int at_bytes) {
 template <int D, int G, int CPL, class VT, class AT>
 struct PermShared {
     static constexpr int RQ = RecShape<D, VT>::RQ, NG = kWave / G;
-    int4 rec[kWave * RQ];
+    int4 rec[NG * staged_group_stride(G, RQ)];
     AT part[2 * NG][G * CPL];
     int pkey[2 * NG];
 };
@@ -440,12 +448,14 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[c] = 0;
 
+    constexpr int GS = staged_group_stride(G, RQ);
+    const int slot = g * GS + gl * RQ;  // this lane's staging slot
     for (int b = 0; b < nb; ++b) {
         if (b * G + gl < glen) {
-            sm.rec[lane * RQ] = rc0;
-            if constexpr (RQ == 2) sm.rec[lane * RQ + 1] = rc1;
+            sm.rec[slot] = rc0;
+            if constexpr (RQ == 2) sm.rec[slot + 1] = rc1;
             if (vovr != nullptr)
-                rec_set_value<VT, RW>(reinterpret_cast<int *>(&sm.rec[lane * RQ]), vo);
+                rec_set_value<VT, RW>(reinterpret_cast<int *>(&sm.rec[slot]), vo);
         }
         wave_sync();
         if (gsrec != nullptr) {
@@ -465,7 +475,7 @@ __device__ __forceinline__ void perm_wave_chunk(PermShared<D, G, CPL, VT, AT> &s
         }
 
         const int cnt = glen - b * G < G ? glen - b * G : G;
-        const int4 *sr = &sm.rec[g * G * RQ];
+        const int4 *sr = &sm.rec[g * GS];
         for (int s0 = 0; s0 < cnt; s0 += U) {
             AT t[U][CPL];
             AT xv[U];
@@ -979,8 +989,9 @@ __device__ __forceinline__ void privatized_block_unit(int4 *smem4, const int4 *_
     constexpr int RW = RecShape<D, VT>::RW, RQ = RecShape<D, VT>::RQ;
     constexpr int RP = G * CPL;
     constexpr int U = UnrollFor<KERNEL_ATOMIC, G, CPL, FT>::value;
-    int4 *s_rec = smem4 + (threadIdx.x >> 6) * (kWave * RQ);
-    AT *pvals = reinterpret_cast<AT *>(smem4 + (kBlock / kWave) * kWave * RQ);
+    constexpr int GS = staged_group_stride(G, RQ);
+    int4 *s_rec = smem4 + (threadIdx.x >> 6) * ((kWave / G) * GS);
+    AT *pvals = reinterpret_cast<AT *>(smem4 + (kBlock / kWave) * (kWave / G) * GS);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane / G, gl = lane % G;
@@ -1005,10 +1016,11 @@ __device__ __forceinline__ void privatized_block_unit(int4 *smem4, const int4 *_
         const int off = b * kWave + lane;
         if (off < len) {
             const int4 *r = rec + (c0 + off) * RQ;
-            s_rec[lane * RQ] = r[0];
-            if constexpr (RQ == 2) s_rec[lane * RQ + 1] = r[1];
+            s_rec[g * GS + gl * RQ] = r[0];
+            if constexpr (RQ == 2) s_rec[g * GS + gl * RQ + 1] = r[1];
             if (vovr != nullptr)
-                rec_set_value<VT, RW>(reinterpret_cast<int *>(&s_rec[lane * RQ]), vovr[c0 + off]);
+                rec_set_value<VT, RW>(reinterpret_cast<int *>(&s_rec[g * GS + gl * RQ]),
+                                      vovr[c0 + off]);
         }
         wave_sync();
         int cnt = len - b * kWave - g * G;
@@ -1022,8 +1034,8 @@ __device__ __forceinline__ void privatized_block_unit(int4 *smem4, const int4 *_
                 kk[u] = -1;
                 if (s < cnt) {
                     int w[RW];
-                    lds_record<RQ>(&s_rec[(g * G + s) * RQ], w);
-                    kk[u] = lds_sub<RW>(&s_rec[(g * G + s) * RQ], n);
+                    lds_record<RQ>(&s_rec[g * GS + s * RQ], w);
+                    kk[u] = lds_sub<RW>(&s_rec[g * GS + s * RQ], n);
                     entry_product<D, RW, CPL, FT, VT, AT>(w, om, rowbytes, colbytes, lam, t[u]);
                 }
             }
@@ -1100,8 +1112,9 @@ inline int capacity_chunk(int64_t P, int64_t cap, int dflt) {
 }
 
 template <class AT>
-inline size_t privatized_smem_bytes(int RQ, int In, int RP) {
-    return (size_t)(kBlock / kWave) * kWave * RQ * 16 + (size_t)In * RP * sizeof(AT);
+inline size_t privatized_smem_bytes(int RQ, int G, int In, int RP) {
+    return (size_t)(kBlock / kWave) * (kWave / G) * staged_group_stride(G, RQ) * 16 +
+           (size_t)In * RP * sizeof(AT);
 }
 
 template <int D, int G, int CPL, class FT, class VT, class AT>
@@ -1146,7 +1159,7 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
             *a.query_chunk = a.chunk;
             return SPT_OK;
         }
-        const size_t smem = privatized_smem_bytes<AT>(RecShape<D, VT>::RQ, a.In, G * CPL);
+        const size_t smem = privatized_smem_bytes<AT>(RecShape<D, VT>::RQ, G, a.In, G * CPL);
         hipLaunchKernelGGL((k_mttkrp_privatized<D, G, CPL, FT, VT, AT>), dim3(grid), dim3(kBlock),
                            smem, a.stream, a.rec, a.P, a.n, a.R, A, a.lambda, vovr, V, a.chunk,
                            a.In);
