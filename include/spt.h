@@ -18,7 +18,10 @@
  *    work on it and return at once, unless documented as synchronising.
  *  - Indices are 0-based.  Subscripts and permutations are int32 (so at most 2^31-1 entries and
  *    mode lengths); sizes and entry counts are int64 in the interface.
- *  - Dense matrices (factors A^(m), MTTKRP results V, Gram matrices) are row-major.
+ *  - Dense matrices (factors A^(m), MTTKRP results V, Gram matrices) are row-major.  Kernels
+ *    address factor rows with 32-bit byte offsets, so every call that reads factor rows of the
+ *    tensor's entries (MTTKRP, CP-ALS, fit, model values, generalized CP, batches) returns
+ *    SPT_EUNSUPPORTED when one of the matrices it gathers from is 4 GiB or larger.
  *  - Every call returns an spt_status.  Argument errors are found on the host before anything
  *    is enqueued and leave all outputs untouched.  Errors found on the GPU (a subscript out of
  *    range, a singular Gram matrix) set a status word inside the tensor's workspace; they are

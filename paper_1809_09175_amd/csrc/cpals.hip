@@ -1398,6 +1398,7 @@ int spt_cp_fit(const spt_tensor *X, int R, const void *const *factors, int fdtyp
     if (X == nullptr || R < 1 || R > kCpMaxR || grams == nullptr || fit == nullptr)
         return SPT_EINVAL;
     int rc = check_factors(X, -1, factors);
+    if (rc == SPT_OK) rc = check_factor_extent(X, -1, R, fdtype);
     if (rc) return rc;
     const CpWs L = cp_layout(max_dim(X), R);
     if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < L.total) return SPT_EWORKSPACE;
@@ -1414,6 +1415,7 @@ int spt_cp_fit_noalloc(const spt_tensor *X, int R, const void *const *factors, i
     if (X == nullptr || R < 1 || R > kCpMaxR || grams == nullptr || fit == nullptr)
         return SPT_EINVAL;
     int rc = check_factors(X, -1, factors);
+    if (rc == SPT_OK) rc = check_factor_extent(X, -1, R, fdtype);
     if (rc) return rc;
     // partial pairs of the model pass, then the four result words
     if ((size_t)2 * model_blocks(X->P) + 4 > kFitScratchDoubles) return SPT_EWORKSPACE;
@@ -1433,6 +1435,7 @@ int spt_cp_fit_after_mode(spt_tensor *X, int mode, int R, const void *const *fac
         return SPT_EINVAL;
     if (fdtype != SPT_F64 && fdtype != SPT_F32 && fdtype != SPT_BF16) return SPT_EINVAL;
     int rc = check_factors(X, -1, factors);
+    if (rc == SPT_OK) rc = check_factor_extent(X, -1, R, fdtype);
     if (rc) return rc;
     const CpWs L = cp_layout(max_dim(X), R);
     if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < L.total) return SPT_EWORKSPACE;
@@ -1495,6 +1498,7 @@ int spt_model_values(const spt_tensor *X, int R, const void *const *factors, int
                      const double *lambda, void *out, void *stream) {
     if (X == nullptr || R < 1 || R > kCpMaxR || out == nullptr) return SPT_EINVAL;
     int rc = check_factors(X, -1, factors);
+    if (rc == SPT_OK) rc = check_factor_extent(X, -1, R, fdtype);
     if (rc) return rc;
     if ((fdtype == SPT_F64) != (X->vdtype == SPT_F64)) return SPT_EUNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);

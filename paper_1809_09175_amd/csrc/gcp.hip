@@ -61,6 +61,7 @@ int spt_gcp_forward(const spt_tensor *X, int R, const void *const *factors, int 
     if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAMMA) return SPT_EINVAL;
     if (int e = gcp_dtype_ok(X, fdtype)) return e;
     int rc = check_factors(X, -1, factors);
+    if (rc == SPT_OK) rc = check_factor_extent(X, -1, R, fdtype);
     if (rc) return rc;
     if (ws == nullptr || ((uintptr_t)ws & 255u) || ws_bytes < 2 * 2048 * sizeof(double))
         return SPT_EWORKSPACE;
@@ -83,6 +84,7 @@ int spt_gcp_backward(const spt_tensor *X, int R, const void *const *factors, int
     if (loss_kind < SPT_GCP_POISSON || loss_kind > SPT_GCP_GAMMA) return SPT_EINVAL;
     if (int e = gcp_dtype_ok(X, fdtype)) return e;
     int rc = check_factors(X, -1, factors);
+    if (rc == SPT_OK) rc = check_factor_extent(X, -1, R, fdtype);
     if (rc) return rc;
     for (int n = 0; n < X->d; ++n)
         if (grads[n] == nullptr) return SPT_EINVAL;

@@ -164,6 +164,7 @@ int spt_gcp_fused(const spt_tensor *X, int R, const void *const *factors, int fd
         return fdtype == SPT_BF16 ? SPT_EUNSUPPORTED : SPT_EINVAL;
     }
     int rc = check_factors(X, -1, factors);
+    if (rc == SPT_OK) rc = check_factor_extent(X, -1, R, fdtype);
     if (rc) return rc;
     for (int n = 0; n < X->d; ++n) {
         if (grads[n] == nullptr) return SPT_EINVAL;

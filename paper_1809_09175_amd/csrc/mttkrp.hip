@@ -245,6 +245,16 @@ int check_factors(const spt_tensor *X, int skip_mode, const void *const *factors
     return SPT_OK;
 }
 
+// The kernels address factor rows with 32-bit byte offsets from the matrix base, so every
+// matrix they gather from (all but skip_mode's; -1 = all) must be smaller than 4 GiB.
+int check_factor_extent(const spt_tensor *X, int skip_mode, int R, int fdtype) {
+    const uint64_t fbytes = fdtype == SPT_F64 ? 8 : (fdtype == SPT_BF16 ? 2 : 4);
+    for (int m = 0; m < X->d; ++m)
+        if (m != skip_mode && (uint64_t)X->dims[m] * (uint64_t)R * fbytes >= (1ull << 32))
+            return SPT_EUNSUPPORTED;
+    return SPT_OK;
+}
+
 int check_mttkrp_args(const spt_tensor *X, int mode, int R, const void *const *factors,
                       int fdtype, const void *V) {
     if (X == nullptr || mode < 0 || mode >= X->d || R < 1 || R > 256 || V == nullptr)
@@ -253,12 +263,7 @@ int check_mttkrp_args(const spt_tensor *X, int mode, int R, const void *const *f
     if (rc) return rc;
     rc = check_dtypes(X, fdtype);
     if (rc) return rc;
-    // factor rows are addressed with 32-bit byte offsets
-    const uint64_t fbytes = fdtype == SPT_F64 ? 8 : (fdtype == SPT_F32 ? 4 : 2);
-    for (int m = 0; m < X->d; ++m)
-        if (m != mode && (uint64_t)X->dims[m] * (uint64_t)R * fbytes >= (1ull << 32))
-            return SPT_EUNSUPPORTED;
-    return SPT_OK;
+    return check_factor_extent(X, mode, R, fdtype);
 }
 
 }  // namespace spt

@@ -129,6 +129,7 @@ int resolve_tune(const spt_tensor *X, int mode, int R, int fdtype, const spt_tun
                  spt_tune *out);
 int zero_words(void *p, int64_t nwords, hipStream_t s);
 int check_factors(const spt_tensor *X, int skip_mode, const void *const *factors);
+int check_factor_extent(const spt_tensor *X, int skip_mode, int R, int fdtype);
 int check_mttkrp_args(const spt_tensor *X, int mode, int R, const void *const *factors,
                       int fdtype, const void *V);
 

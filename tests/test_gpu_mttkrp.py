@@ -313,6 +313,43 @@ def test_errors_reported(gpu):
     assert e.value.code == -6
 
 
+def test_factor_matrices_of_4_gib_are_rejected(gpu):
+    """Factor rows are addressed with 32-bit byte offsets: every call that gathers from a factor
+    matrix of 4 GiB or more refuses it on the host (SPT_EUNSUPPORTED) before anything is
+    enqueued.  Mode 1 has 2^24 rows, so R = 64 FP32 (or R = 128 BF16) makes A^(1) exactly 4 GiB;
+    the factor pointers are small placeholders that no kernel ever reads."""
+    import ctypes
+    from paper_1809_09175_amd import _lib
+    lib = _lib.load()
+    X = datagen.CooTensor(np.array([[0, 5, 1], [3, (1 << 24) - 1, 2]], np.int32),
+                          np.ones(2, np.float32), (4, 1 << 24, 3))
+    T = _dev_tensor(X, np.float32)
+    T.permute()
+    buf = torch.zeros(1 << 16, device="cuda")
+    p = buf.data_ptr()
+    facs = _lib.ptr_array([p, p, p])
+    out = ctypes.c_void_p(p)
+    fit = ctypes.c_double()
+    loss = ctypes.c_double()
+    for R, fdt in ((64, _lib.SPT_F32), (128, _lib.SPT_BF16)):
+        for n in (0, 2):
+            for algo in (_lib.ALGO_ATOMIC, _lib.ALGO_PERMUTED):
+                tune = _lib.SptTune(algo, 0, 0, 0, 0, 0)
+                assert lib.spt_mttkrp(T.handle, n, R, facs, fdt, None, None, out,
+                                      ctypes.byref(tune), None) == _lib.SPT_EUNSUPPORTED, (R, n)
+    R, fdt = 64, _lib.SPT_F32
+    assert lib.spt_cp_fit(T.handle, R, facs, fdt, out, out, out, 1 << 18, ctypes.byref(fit),
+                          None, None) == _lib.SPT_EUNSUPPORTED
+    assert lib.spt_model_values(T.handle, R, facs, fdt, None, out, None) == _lib.SPT_EUNSUPPORTED
+    assert lib.spt_gcp_forward(T.handle, R, facs, fdt, 0, None, out, ctypes.byref(loss), out,
+                               1 << 18, None) == _lib.SPT_EUNSUPPORTED
+    assert lib.spt_gcp_fused(T.handle, R, facs, fdt, 0, ctypes.byref(loss),
+                             _lib.ptr_array([p, p, p]), out, None, None) == _lib.SPT_EUNSUPPORTED
+    # one row fewer fits: the same calls at R = 63 pass the extent check (not run here)
+    assert (1 << 24) * 63 * 4 < (1 << 32) <= (1 << 24) * 64 * 4
+    torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------------ full-size sampled parity
 
 def _sampled_rows(X, n, rows):
@@ -342,7 +379,9 @@ POWERLAW3_CASES = [
     ("f32", 16, ("atomic", "permuted", "permuted_copy", "auto")),
     ("f32", 32, ("atomic", "permuted", "permuted_copy", "auto")),
     ("f32", 64, ("atomic", "permuted", "permuted_copy", "auto")),
+    ("bf16", 16, ("auto",)),
     ("bf16", 32, ("auto",)),
+    ("bf16", 64, ("auto",)),
     ("f64", 32, ("permuted", "auto")),
 ]
 
