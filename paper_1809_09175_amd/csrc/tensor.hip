@@ -238,6 +238,15 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t *__restrict__ a, 
 // element order (item, wave, lane).  gofs[d] is the next output position of digit d.  Each
 // sub-tile is first ordered by digit in LDS, then written out with consecutive threads on
 // consecutive positions of a digit's run, so the stores coalesce.
+// Tile of scatter workgroup b of n.  Workgroups go to the eight XCDs in turn, so consecutive
+// ones run on different XCDs; this mapping gives each XCD a contiguous range of tiles, whose
+// digit runs land next to each other in the output and so share lines in that XCD's L2
+// (three-mode permutation of 1e8 keys: 7.19 ms against 7.35).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+    const int64_t x = b & 7, l = b >> 3, per = n >> 3, rem = n & 7;
+    return x * per + (x < rem ? x : rem) + l;
+}
+
 template <bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const int32_t *__restrict__ keys, const int32_t *__restrict__ vals,
@@ -250,10 +259,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     __shared__ int32_t lkey[kSortSub];
     __shared__ int32_t lval[kSortSub];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    gofs[tid] = offsets[(int64_t)tid * ntiles + blockIdx.x];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);  // the grid is one workgroup per tile
+    gofs[tid] = offsets[(int64_t)tid * ntiles + tile];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int sub = 0; sub < kSortSubs; ++sub) {
-        const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)sub * kSortSub;
+        const int64_t base = tile * kSortTile + (int64_t)sub * kSortSub;
         if (base >= P) break;  // uniform
         {
             uint32_t *c32 = reinterpret_cast<uint32_t *>(&cnt[0][0][0]);
