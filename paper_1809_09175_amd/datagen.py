@@ -22,6 +22,11 @@ available; skewed index distributions stand in for real-data contention, Sec. 7.
 
 Every generator takes a ``scale`` (fraction of the entries) and optional dims so the same recipe
 produces small parity-test cases.
+
+  max_entries   3-way 2e6 x 1.5e6 x 1e6 with 2^31 - 1 entries (the int32 limit of the
+                subscripts and permutations), uniform subscripts and U(0,1) FP32 values, drawn
+                on the GPU with torch's seeded generator (too large to draw on the host)
+                                                                        (seed 6)
 """
 from __future__ import annotations
 
@@ -264,3 +269,16 @@ def gcp_counts(scale=1.0, dims=(200_000, 100_000, 5_000), seed=5, R=32):
     A = factors(dims, R, seed + 1000, np.float32, high=c)
     return X, A
 
+
+
+def max_entries(seed=6, dims=(2_000_000, 1_500_000, 1_000_000), nnz=(1 << 31) - 1, device="cuda"):
+    """(subs, vals) as device tensors: nnz x 3 int32 subscripts, uniform per mode, and U(0,1)
+    FP32 values, from torch's Philox-based generator on the device."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    subs = torch.empty((nnz, len(dims)), dtype=torch.int32, device=device)
+    for m, I in enumerate(dims):
+        subs[:, m] = torch.randint(0, I, (nnz,), dtype=torch.int32, device=device, generator=g)
+    vals = torch.rand(nnz, dtype=torch.float32, device=device, generator=g)
+    return subs, vals, tuple(dims)

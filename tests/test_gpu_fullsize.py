@@ -124,3 +124,64 @@ def test_batch64_full_size(gpu):
             assert np.isfinite(got).all(), (rep, i)
             assert _relerr(got, ref) < 1e-5, (rep, i, it["tune"])
     B.close()
+
+
+def test_max_entry_count(gpu):
+    """2^31 - 1 entries, the most that int32 subscripts and permutations allow, so that every
+    index computation of packing, sorting, the sorted copy and the traversals is exercised at
+    its limit (about 180 GB of device memory).  Each mode's permutation is checked on the device
+    against its definition (keys non-decreasing, each key the subscript of the entry it names,
+    equal keys in increasing storage position, every position exactly once); MTTKRP rows (16
+    random rows per mode, about 1,000-2,000 entries each) against the oracle on exactly the
+    entries that feed them, for the atomic and gather traversals and, on mode 0, the
+    second-mode sorted copy."""
+    import paper_1809_09175_amd as spt
+    _log("max entries: drawing 2^31 - 1 entries on the device")
+    subs, vals, dims = datagen.max_entries()
+    P = subs.shape[0]
+    T = spt.SparseTensor(subs, vals, dims)
+    T.validate()
+    T.permute()
+    torch.cuda.synchronize()
+    step = 1 << 28
+    for n in range(3):
+        _log(f"max entries: permutation of mode {n}")
+        p, k = T.perm(n)
+        seen = torch.zeros(P, dtype=torch.bool, device="cuda")
+        for a in range(0, P, step):
+            b = min(P, a + step + 1)  # one element of overlap for the adjacent-pair checks
+            pa = p[a:b].long()
+            ka = k[a:b]
+            assert bool((ka[1:] >= ka[:-1]).all()), (n, a)
+            eq = ka[1:] == ka[:-1]
+            assert bool((pa[1:][eq] > pa[:-1][eq]).all()), (n, a)
+            assert torch.equal(subs[pa, n], ka), (n, a)
+            seen[pa] = True
+            del pa, ka, eq
+        assert bool(seen.all()), n
+        del seen
+    R = 16
+    a32 = [a.astype(np.float32) for a in datagen.factors(dims, R, 61, np.float64)]
+    ref = [a.astype(np.float64) for a in a32]
+    dev = [torch.from_numpy(a).cuda() for a in a32]
+    _log("max entries: second-mode sorted copy of mode 0")
+    T.sort_copy(0)
+    rng = np.random.default_rng(62)
+    for n in range(3):
+        rows = np.unique(rng.integers(0, dims[n], size=16))
+        rows_t = torch.from_numpy(rows.astype(np.int32)).cuda()
+        idx = torch.cat([torch.nonzero(torch.isin(subs[a:a + step, n], rows_t)).flatten() + a
+                         for a in range(0, P, step)])
+        s_h = subs[idx].cpu().numpy()
+        v_h = vals[idx].cpu().numpy()
+        _log(f"max entries: mode {n}, oracle on {len(v_h)} entries")
+        V_ref = oracle.mttkrp(s_h, v_h, dims, ref, n)[rows]
+        for algo in ["atomic", "permuted"] + (["permuted_copy"] if n == 0 else []):
+            _log(f"max entries: mode {n} {algo}")
+            V = spt.mttkrp(T, dev, n, algo=algo)
+            torch.cuda.synchronize()
+            got = V[torch.from_numpy(rows).cuda()].cpu().numpy()
+            assert _relerr(got, V_ref) < 1e-5, (n, algo)
+            del V
+    del T, subs, vals
+    torch.cuda.empty_cache()
