@@ -185,3 +185,50 @@ def test_max_entry_count(gpu):
             del V
     del T, subs, vals
     torch.cuda.empty_cache()
+
+
+def test_max_mode_length(gpu):
+    """A mode of 2^31 - 1 rows (the int32 limit): 31-bit keys take four radix passes, and V
+    (2^31 - 1 rows x R) is addressed beyond 32-bit element offsets.  The permutation against a
+    host stable sort, and the rows of V the entries feed against the oracle evaluated with the
+    used rows renumbered densely (V's rows are independent, so this changes no arithmetic), for
+    the atomic, gather and sorted-copy traversals; rows no entry feeds stay zero."""
+    import paper_1809_09175_amd as spt
+    rng = np.random.default_rng(71)
+    I0 = (1 << 31) - 1
+    dims = (I0, 5, 3)
+    P = 1_000_003
+    subs = np.stack([rng.integers(0, I0, size=P), rng.integers(0, 5, size=P),
+                     rng.integers(0, 3, size=P)], 1).astype(np.int32)
+    subs[:3, 0] = [I0 - 1, 0, I0 - 1]          # the first and the last row
+    vals = rng.random(P).astype(np.float32)
+    T = spt.SparseTensor(torch.from_numpy(subs).cuda(), torch.from_numpy(vals).cuda(), dims)
+    T.validate()
+    T.permute()
+    p, k = T.perm(0)
+    ref_order = np.argsort(subs[:, 0], kind="stable")
+    assert np.array_equal(p.cpu().numpy(), ref_order)
+    assert np.array_equal(k.cpu().numpy(), subs[ref_order, 0])
+    T.sort_copy(0)
+    R = 2
+    a32 = [a.astype(np.float32) for a in datagen.factors((1, 5, 3), R, 72, np.float64)]
+    dev = [None, torch.from_numpy(a32[1]).cuda(), torch.from_numpy(a32[2]).cuda()]  # A^(0) unread
+    used, dense = np.unique(subs[:, 0], return_inverse=True)
+    s_dense = subs.copy()
+    s_dense[:, 0] = dense
+    V_ref = oracle.mttkrp(s_dense, vals, (len(used), 5, 3), [np.zeros((len(used), R))] +
+                          [a.astype(np.float64) for a in a32[1:]], 0)
+    pick = np.unique(np.concatenate([[0, len(used) - 1], rng.integers(0, len(used), 2000)]))
+    rows_t = torch.from_numpy(used[pick].astype(np.int64)).cuda()
+    unused = [1, I0 - 2]
+    assert not np.isin(unused, used).any()
+    for algo in ("atomic", "permuted", "permuted_copy"):
+        _log(f"max mode length: {algo}")
+        V = spt.mttkrp(T, dev, 0, algo=algo)
+        torch.cuda.synchronize()
+        assert V.shape == (I0, R)
+        got = V[rows_t].cpu().numpy()
+        assert _relerr(got, V_ref[pick]) < 1e-5, algo
+        assert float(V[torch.tensor(unused, device="cuda")].abs().max()) == 0.0, algo
+        del V
+        torch.cuda.empty_cache()
