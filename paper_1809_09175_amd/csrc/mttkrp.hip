@@ -65,14 +65,15 @@ static int pow2_at_least(int x) {
 // (lanes x FP32 columns) at R = 16, 32, 64, and with 8 x 2, 16 x 2 and 8 x 8 for BF16 factors
 // (2.65, 2.90 and 4.47 ms for three modes, against 2.75-2.85, 2.92 and 4.82 with 16 x 1,
 // 16 x 2 and 32 x 2); i.e. one FP32 column per lane below 32 columns, then four; BF16 one column
-// below 16, two up to 32, eight up to 64 (sixteen bytes per lane), two above; FP64 four
+// below 16, two up to 32, then eight (sixteen bytes per lane; R = 128: 16 x 8 7.6-8.2 ms against
+// 8.8-9.0 with 64 x 2); FP64 four
 // columns per lane from R = 16 (4 x 4, 8 x 4, 16 x 4: 4.53, 7.30, 13.8 ms against 7.84, 7.61,
 // 14.6 with 16 x 1 and the FP32 chunk rules); over as many lanes as cover R.  The atomic kernel is fastest with one column per lane (its LDS
 // and global atomics are per column either way).  Columns per lane must divide R.
 static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out) {
     int cpl = 1, G = 8;
     if (algo == SPT_ALGO_PERMUTED) {
-        int c = (fdtype == SPT_BF16)  ? (R < 16 ? 1 : (R <= 32 ? 2 : (R <= 64 ? 8 : 2)))
+        int c = (fdtype == SPT_BF16)  ? (R < 16 ? 1 : (R <= 32 ? 2 : 8))
                 : (fdtype == SPT_F64) ? (R < 16 ? 1 : (R <= 64 ? 4 : 8))
                                       : (R < 32 ? 1 : (R <= 64 ? 4 : 8));
         while (c > 1 && R % c != 0) c >>= 1;

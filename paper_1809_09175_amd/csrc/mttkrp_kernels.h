@@ -1127,10 +1127,11 @@ int launch_cfg(const MttkrpArgs &a, const FactorSet<FT> &A) {
     if (a.algo == SPT_ALGO_PERMUTED || a.algo == SPT_ALGO_PERMUTED_COPY) {
         int chunk = a.chunk;
         if (a.auto_chunk && a.slot_keys == nullptr && a.srec != nullptr && CPL >= 4 &&
-            sizeof(FT) <= 4) {
+            (sizeof(FT) == 2 || (sizeof(FT) == 4 && a.R <= 64))) {
             // resident wavefronts of this instantiation on the whole device (queried once);
-            // FP64 factors keep the default chunk (8192-entry chunks ran 4% faster at R = 32
-            // than the matched 24-32k ones)
+            // FP64 factors, and FP32 ones above R = 64, keep the default chunk (8192-entry
+            // chunks ran 4% faster than the matched 24-32k ones at R = 32 in FP64, 4096-entry
+            // chunks 3.5% faster at R = 128 in FP32)
             static const int per_cu = [] {
                 int nb = 0;
                 if (hipOccupancyMaxActiveBlocksPerMultiprocessor(

@@ -179,6 +179,12 @@ CASES = [
     ("bf16", (500, 400, 30), 100_000, (1.1, 1.1, 1.1), 32),
     ("bf16", (3000, 20, 9), 50_001, (1.2, 0.0, 1.1), 64),
     ("bf16", (100, 90, 80), 20_000, (0.0, 0.0, 0.0), 9),
+    ("bf16", (1000, 1000, 1000), 60_000, (1.1, 1.1, 1.1), 128),
+    ("bf16", (1000, 1000, 1000), 30_000, (1.1, 1.1, 1.1), 72),
+    # the smallest ranks: one column (most lanes of a group idle), two, three
+    ("f32", (500, 400, 30), 30_001, (1.1, 1.1, 1.1), 1),
+    ("bf16", (500, 400, 30), 30_001, (1.1, 1.1, 1.1), 2),
+    ("f64", (300, 200, 100), 20_000, (1.1, 0.0, 0.0), 3),
 ]
 
 
