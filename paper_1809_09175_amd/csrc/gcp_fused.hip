@@ -105,6 +105,8 @@ static int launch_fused_d(const FusedArgs &a, const FactorSet<FT> &A, int G, int
         case 16 * 16 + 8: return launch_fused_cfg<D, 16, 8, FT>(a, A);
         case 32 * 16 + 1: return launch_fused_cfg<D, 32, 1, FT>(a, A);
         case 32 * 16 + 2: return launch_fused_cfg<D, 32, 2, FT>(a, A);
+        case 32 * 16 + 4: return launch_fused_cfg<D, 32, 4, FT>(a, A);
+        case 32 * 16 + 8: return launch_fused_cfg<D, 32, 8, FT>(a, A);
         case 64 * 16 + 1: return launch_fused_cfg<D, 64, 1, FT>(a, A);
         case 64 * 16 + 2: return launch_fused_cfg<D, 64, 2, FT>(a, A);
         case 64 * 16 + 4: return launch_fused_cfg<D, 64, 4, FT>(a, A);

@@ -32,7 +32,7 @@ static bool cfg_supported(int G, int CPL) {
         case 4 * 16 + 4: case 4 * 16 + 8:
         case 8 * 16 + 1: case 8 * 16 + 2: case 8 * 16 + 4: case 8 * 16 + 8:
         case 16 * 16 + 1: case 16 * 16 + 2: case 16 * 16 + 4: case 16 * 16 + 8:
-        case 32 * 16 + 1: case 32 * 16 + 2:
+        case 32 * 16 + 1: case 32 * 16 + 2: case 32 * 16 + 4: case 32 * 16 + 8:
         case 64 * 16 + 1: case 64 * 16 + 2: case 64 * 16 + 4:
             return true;
         default:
@@ -60,22 +60,25 @@ static int pow2_at_least(int x) {
     return p;
 }
 
-// Default lane layout, from measurements on MI355X (1e8-entry Zipf tensor, R = 16/32/64, each
-// layout at its best unroll): the permuted kernel is fastest with 16 x 1, 8 x 4 and 16 x 4
-// (lanes x FP32 columns) at R = 16, 32, 64, and with 8 x 2, 16 x 2 and 8 x 8 for BF16 factors
-// (2.65, 2.90 and 4.47 ms for three modes, against 2.75-2.85, 2.92 and 4.82 with 16 x 1,
-// 16 x 2 and 32 x 2); i.e. one FP32 column per lane below 32 columns, then four; BF16 one column
-// below 16, two up to 32, then eight (sixteen bytes per lane; R = 128: 16 x 8 7.6-8.2 ms against
-// 8.8-9.0 with 64 x 2); FP64 four
-// columns per lane from R = 16 (4 x 4, 8 x 4, 16 x 4: 4.53, 7.30, 13.8 ms against 7.84, 7.61,
-// 14.6 with 16 x 1 and the FP32 chunk rules); over as many lanes as cover R.  The atomic kernel is fastest with one column per lane (its LDS
-// and global atomics are per column either way).  Columns per lane must divide R.
+// Default lane layout (lanes per entry x columns per lane), from measurements on MI355X
+// (1e8-entry Zipf tensor, all three modes, each layout at its best unroll and chunk):
+//   FP32  16 x 1 at R = 16, then four columns (sixteen bytes per lane): 8 x 4, 16 x 4, 32 x 4,
+//         64 x 4 at R = 32, 64, 128, 256 (R = 128 / 256: 12.4 / 25.6 ms against 14.0 / 28.1
+//         with 16 x 8 / 32 x 8);
+//   BF16  one column below R = 16, two up to 32, then eight (sixteen bytes per lane): 8 x 2,
+//         16 x 2, 8 x 8, 16 x 8, 32 x 8 at R = 16, 32, 64, 128, 256 (R = 16 / 64 / 128:
+//         2.65 / 4.47 / 7.5 ms against 2.75-2.85 / 4.82 / 9.0 with 16 x 1 / 32 x 2 / 64 x 2);
+//   FP64  four columns (32 bytes per lane) from R = 16: 4 x 4, 8 x 4, 16 x 4, 32 x 4 at R = 16,
+//         32, 64, 128 (4.53 / 7.30 / 13.8 / 28.2 ms against 7.84 / 7.61 / 14.6 / 36.1 with
+//         16 x 1 and the FP32 chunk rules at R <= 64, 16 x 8 at R = 128);
+// over as many lanes as cover R.  The atomic kernel is fastest with one column per lane (its
+// LDS and global atomics are per column either way).  Columns per lane must divide R.
 static void default_layout(int R, int fdtype, int algo, int *G_out, int *cpl_out) {
     int cpl = 1, G = 8;
     if (algo == SPT_ALGO_PERMUTED) {
         int c = (fdtype == SPT_BF16)  ? (R < 16 ? 1 : (R <= 32 ? 2 : 8))
-                : (fdtype == SPT_F64) ? (R < 16 ? 1 : (R <= 64 ? 4 : 8))
-                                      : (R < 32 ? 1 : (R <= 64 ? 4 : 8));
+                : (fdtype == SPT_F64) ? (R < 16 ? 1 : 4)
+                                      : (R < 32 ? 1 : 4);
         while (c > 1 && R % c != 0) c >>= 1;
         int g = pow2_at_least((R + c - 1) / c);
         const int gmin = (fdtype == SPT_F64 && c == 4) ? 4 : 8;

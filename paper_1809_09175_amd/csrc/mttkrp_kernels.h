@@ -1195,6 +1195,8 @@ int launch_d(const MttkrpArgs &a, const FactorSet<FT> &A, int G, int CPL) {
         case 16 * 16 + 8: return launch_cfg<D, 16, 8, FT, VT, AT>(a, A);
         case 32 * 16 + 1: return launch_cfg<D, 32, 1, FT, VT, AT>(a, A);
         case 32 * 16 + 2: return launch_cfg<D, 32, 2, FT, VT, AT>(a, A);
+        case 32 * 16 + 4: return launch_cfg<D, 32, 4, FT, VT, AT>(a, A);
+        case 32 * 16 + 8: return launch_cfg<D, 32, 8, FT, VT, AT>(a, A);
         case 64 * 16 + 1: return launch_cfg<D, 64, 1, FT, VT, AT>(a, A);
         case 64 * 16 + 2: return launch_cfg<D, 64, 2, FT, VT, AT>(a, A);
         case 64 * 16 + 4: return launch_cfg<D, 64, 4, FT, VT, AT>(a, A);

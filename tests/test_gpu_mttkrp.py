@@ -217,7 +217,8 @@ def test_mttkrp_parity(gpu, case, algo):
 def _configs_for(R, kind):
     out = []
     for lanes, cols in [(4, 4), (4, 8), (8, 1), (8, 2), (8, 4), (8, 8), (16, 1), (16, 2),
-                        (16, 4), (16, 8), (32, 1), (32, 2), (64, 1), (64, 2), (64, 4)]:
+                        (16, 4), (16, 8), (32, 1), (32, 2), (32, 4), (32, 8), (64, 1), (64, 2),
+                        (64, 4)]:
         if lanes * cols >= R and R % cols == 0:
             out.append((lanes, cols))
     return out
