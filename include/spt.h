@@ -77,8 +77,8 @@ typedef enum spt_algo {
 /* Launch parameters of one MTTKRP.  Zero fields take the default.  A lane group of
  * lanes_per_nnz lanes evaluates one entry, each lane holding cols_per_lane consecutive rank
  * columns; the product must cover R and cols_per_lane must divide R.  Compiled (lanes, cols)
- * pairs: (4,4) (4,8) (8,1) (8,2) (8,4) (8,8) (16,1) (16,2) (16,4) (16,8) (32,1) (32,2) (64,1)
- * (64,2) (64,4).  nnz_per_wave: entries one wavefront walks (a multiple of 64); the atomic
+ * pairs: (4,4) (4,8) (8,1) (8,2) (8,4) (8,8) (16,1) (16,2) (16,4) (16,8) (32,1) (32,2) (32,4)
+ * (32,8) (64,1) (64,2) (64,4).  nnz_per_wave: entries one wavefront walks (a multiple of 64); the atomic
  * algorithm gives each workgroup 4 x nnz_per_wave entries rounded up to whole sorted tiles. */
 typedef struct spt_tune {
     int32_t algo;

@@ -131,8 +131,9 @@ static int launch_fused(const FusedArgs &a, int d, const void *const *factors, i
 // columns each), since every entry ends in a butterfly over its lane group.  Measured on the
 // 1e8-entry count tensor at R = 32: 4 x 8 lanes x columns 8.5 ms, 8 x 4 9.8 ms, 16 x 2 16.9 ms.
 static bool gcp_layout(int R, int *G, int *CPL) {
-    static const int ok[][2] = {{4, 4},  {4, 8},  {8, 1},  {8, 2},  {8, 4},  {8, 8},  {16, 1}, {16, 2},
-                                {16, 4}, {16, 8}, {32, 1}, {32, 2}, {64, 1}, {64, 2}, {64, 4}};
+    static const int ok[][2] = {{4, 4},  {4, 8},  {8, 1},  {8, 2},  {8, 4},  {8, 8},
+                                {16, 1}, {16, 2}, {16, 4}, {16, 8}, {32, 1}, {32, 2},
+                                {32, 4}, {32, 8}, {64, 1}, {64, 2}, {64, 4}};
     for (int c = 8; c >= 1; c >>= 1) {
         if (R % c != 0 || R / c < 4) continue;
         int g = 1;

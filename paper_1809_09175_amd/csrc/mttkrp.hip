@@ -378,9 +378,9 @@ extern "C" int spt_mttkrp_autotune(const spt_tensor *X, int mode, int R,
     if (reps < 1) reps = kTuneDefaultReps;
     if (reps > kTuneMaxReps) reps = kTuneMaxReps;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    static const int cfgs[][2] = {{4, 4},  {4, 8},  {8, 1},  {8, 2},  {8, 4},
-                                  {8, 8},  {16, 1}, {16, 2}, {16, 4}, {16, 8},
-                                  {32, 1}, {32, 2}, {64, 1}, {64, 2}, {64, 4}};
+    static const int cfgs[][2] = {{4, 4},  {4, 8},  {8, 1},  {8, 2},  {8, 4},  {8, 8},
+                                  {16, 1}, {16, 2}, {16, 4}, {16, 8}, {32, 1}, {32, 2},
+                                  {32, 4}, {32, 8}, {64, 1}, {64, 2}, {64, 4}};
     static const int chunks[] = {512, 1024, 2048, 4096};
     const bool batch_only = (flags & SPT_TUNE_BATCH_CONFIGS) != 0;
     hipEvent_t ev[2 * kTuneMaxReps];
