@@ -362,14 +362,14 @@ def bench_gcp(spt, datagen, torch, dev, R=32, steps=3):
 # (--pmc FETCH_SIZE and --pmc WRITE_SIZE runs of the same command)
 # ------------------------------------------------------------------------------------------
 
-PROFILE_CMD = ("cd /tmp && export TMPDIR=/tmp && R=<repository root>; "
-               "rocprofv3 --kernel-trace --stats -f csv -d $R/gpurun_out/pc/prof_trace -o run -- "
+PROFILE_CMD = ("cd /tmp && export TMPDIR=/tmp && R=<repository root> && OUT=<output directory>; "
+               "rocprofv3 --kernel-trace --stats -f csv -d $OUT/prof_trace -o run -- "
                "python3 $R/bench.py --profile; then, each in a run of its own: "
-               "rocprofv3 --pmc FETCH_SIZE -f csv -d $R/gpurun_out/pc/prof_fetch -o run -- "
+               "rocprofv3 --pmc FETCH_SIZE -f csv -d $OUT/prof_fetch -o run -- "
                "python3 $R/bench.py --profile; "
-               "rocprofv3 --pmc WRITE_SIZE -f csv -d $R/gpurun_out/pc/prof_write -o run -- "
+               "rocprofv3 --pmc WRITE_SIZE -f csv -d $OUT/prof_write -o run -- "
                "python3 $R/bench.py --profile; then, from the repository root: "
-               "python3 bench.py --summarize-profile gpurun_out/pc")
+               "python3 bench.py --summarize-profile $OUT")
 TRIAD_READ_BYTES = 2 * (1 << 28) * 4   # the --profile triad reads b and c (2^28 floats each)
 TRIAD_WRITE_BYTES = (1 << 28) * 4      # and writes a
 
