@@ -140,13 +140,24 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const int32_t *__restrict
     h[threadIdx.x] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    // the next sub-tile's digits are loaded while the current one is counted
+    uint32_t pdg[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t e = (int64_t)blockIdx.x * kSortTile + it * kBlock + threadIdx.x;
+        pdg[it] = (e < P) ? (((uint32_t)sort_key<FIRST>(keys, recw, rw, n, e) >> shift) & 255u) : 256u;
+    }
     for (int sub = 0; sub < kSortSubs; ++sub) {
         const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)sub * kSortSub;
         uint32_t dgs[kSortItems];
 #pragma unroll
-        for (int it = 0; it < kSortItems; ++it) {
-            const int64_t e = base + it * kBlock + threadIdx.x;
-            dgs[it] = (e < P) ? (((uint32_t)sort_key<FIRST>(keys, recw, rw, n, e) >> shift) & 255u) : 256u;
+        for (int it = 0; it < kSortItems; ++it) dgs[it] = pdg[it];
+        if (sub + 1 < kSortSubs) {
+#pragma unroll
+            for (int it = 0; it < kSortItems; ++it) {
+                const int64_t e = base + kSortSub + it * kBlock + threadIdx.x;
+                pdg[it] = (e < P) ? (((uint32_t)sort_key<FIRST>(keys, recw, rw, n, e) >> shift) & 255u) : 256u;
+            }
         }
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
@@ -262,9 +273,32 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);  // the grid is one workgroup per tile
     gofs[tid] = offsets[(int64_t)tid * ntiles + tile];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // the next sub-tile's keys and values are loaded while the current one is ranked (three-mode
+    // permutation of 1e8 keys: 6.3 ms against 7.2 with each sub-tile's loads waited for in turn)
+    int32_t pk[kSortItems], pv[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t e = tile * kSortTile + it * kBlock + tid;
+        pk[it] = (e < P) ? sort_key<FIRST>(keys, recw, rw, n, e) : 0;
+        pv[it] = (e < P) ? (FIRST ? (int32_t)e : vals[e]) : 0;
+    }
     for (int sub = 0; sub < kSortSubs; ++sub) {
         const int64_t base = tile * kSortTile + (int64_t)sub * kSortSub;
         if (base >= P) break;  // uniform
+        int32_t ck[kSortItems], cv[kSortItems];
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            ck[it] = pk[it];
+            cv[it] = pv[it];
+        }
+        if (sub + 1 < kSortSubs) {
+#pragma unroll
+            for (int it = 0; it < kSortItems; ++it) {
+                const int64_t e = base + kSortSub + it * kBlock + tid;
+                pk[it] = (e < P) ? sort_key<FIRST>(keys, recw, rw, n, e) : 0;
+                pv[it] = (e < P) ? (FIRST ? (int32_t)e : vals[e]) : 0;
+            }
+        }
         {
             uint32_t *c32 = reinterpret_cast<uint32_t *>(&cnt[0][0][0]);
             for (int k = tid; k < kSortItems * (kBlock / kWave) * 128; k += kBlock) c32[k] = 0;
@@ -277,9 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         for (int it = 0; it < kSortItems; ++it) {
             int64_t e = base + it * kBlock + tid;
             bool valid = e < P;
-            int32_t key = valid ? sort_key<FIRST>(keys, recw, rw, n, e) : 0;
-            int32_t val = 0;
-            if (valid) val = FIRST ? (int32_t)e : vals[e];
+            int32_t key = valid ? ck[it] : 0;
+            int32_t val = valid ? cv[it] : 0;
             uint32_t dg = ((uint32_t)key >> shift) & 255u;
             uint64_t m = __ballot(valid);
 #pragma unroll
