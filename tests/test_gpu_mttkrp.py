@@ -386,6 +386,7 @@ POWERLAW3_CASES = [
     ("f32", 16, ("atomic", "permuted", "permuted_copy", "auto")),
     ("f32", 32, ("atomic", "permuted", "permuted_copy", "auto")),
     ("f32", 64, ("atomic", "permuted", "permuted_copy", "auto")),
+    ("f32", 128, ("auto",)),   # the MTTKRP of the CP-ALS sweep at R = 128 (32 x 4 layout)
     ("bf16", 16, ("auto",)),
     ("bf16", 32, ("auto",)),
     ("bf16", 64, ("auto",)),
